@@ -1,0 +1,178 @@
+/*
+ * cglbm.h -- C ABI of liblbm.so: the per-time-step update of the two-colour
+ * D3Q27 colour-gradient lattice Boltzmann model with nonorthogonal central
+ * moments (Saito, De Rosis, Festuccia, Kaneko, Abe, Koyama,
+ * arXiv:1804.08923), on one AMD Instinct MI355X (gfx950).
+ *
+ * What a step computes (Sec. II of the paper):
+ *   colour densities rho_k = sum_i f_i^k, order parameter phi (Eq. order),
+ *   isotropic gradients of phi and rho, interpolated alpha_bar and nu_bar,
+ *   body force F = (rho - rho_b0) g (Eq. bodyForceJet), velocity with the
+ *   half-force term (Eq. Momentum), enhanced equilibrium (Eq. EES, Eq. Phi),
+ *   GMRT central-moment collision and forcing (Eqs. scoll, ketF, ketFd) with
+ *   s0 = s1 = 0 and s2b = s3 = s4 = s5 = s6 = 1, perturbation (Eq. perturb,
+ *   Eq. B_i), recolouring (Eqs. op3r, op3b), streaming (Eq. LBE) and, for the
+ *   jet problem, the inflow, free-slip and convective-outflow boundaries of
+ *   Sec. IV A.
+ *
+ * Conventions shared by every entry point:
+ *   - Lattice: nx*ny*nz nodes, node index n = (z*ny + y)*nx + x (x fastest).
+ *     Directions i = 0..26 follow the paper's velocity set (Eq. velVec).
+ *   - Memory: the caller owns all device memory.  lbm_query_sizes() states
+ *     the size of every buffer; the library stores the raw device pointers
+ *     handed to lbm_init() and never allocates or frees device memory.
+ *   - Streams: every call enqueues work on the stream given to lbm_init()
+ *     (a hipStream_t passed as void*) and does not synchronise the host,
+ *     except where a function says so.  One handle per stream; a handle is
+ *     not thread-safe.
+ *   - Errors: every function returns an int status (LBM_OK or a negative
+ *     LBM_ERR_* code).  No exception crosses the ABI.  lbm_last_error()
+ *     returns a thread-local message describing the last failure.
+ */
+#ifndef CGLBM_H
+#define CGLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_ERR_INVALID_ARG (-1) /* a parameter or pointer failed validation */
+#define LBM_ERR_UNSUPPORTED (-2) /* a valid request this library does not implement */
+#define LBM_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define LBM_ERR_NONFINITE (-4)   /* the FP64 audit found a non-finite total */
+#define LBM_ERR_STATE (-5)       /* call out of order (e.g. step before init) */
+
+enum lbm_bc { LBM_BC_PERIODIC = 0, LBM_BC_JET = 1 };
+enum lbm_storage { LBM_STORAGE_FP32 = 0, LBM_STORAGE_BF16 = 1, LBM_STORAGE_FP16 = 2 };
+enum lbm_init_kind {
+    LBM_INIT_FIELDS = 0,  /* per-colour equilibria of caller fields rho_r, rho_b, u */
+    LBM_INIT_DROPLET = 1, /* tanh droplet of Sec. III at rest */
+    LBM_INIT_JET = 2      /* all blue at rest (Sec. IV A) */
+};
+
+/* Problem parameters in lattice units (c = delta_x = delta_t = 1). */
+typedef struct lbm_params {
+    int32_t nx, ny, nz;   /* lattice size; periodic: >= 1 each; jet: >= 3 each; nz <= 65535; at most 2^29 nodes */
+    int32_t bc;           /* enum lbm_bc */
+    int32_t storage;      /* enum lbm_storage: population storage format */
+    int32_t init;         /* enum lbm_init_kind used by lbm_init */
+    double rho_r0, rho_b0;/* reference densities; gamma = rho_r0 / rho_b0 (Sec. II) */
+    double alpha_b;       /* alpha of the blue phase (the paper: 8/27); alpha_r = 1 - (1 - alpha_b)/gamma */
+    double nu_r, nu_b;    /* kinematic viscosities (> 0); nu_bar is their phi-weighted harmonic mean */
+    double A;             /* perturbation strength; sigma = (4/9) A tau (Eq. sigma) */
+    double beta;          /* recolouring parameter in [0, 1] (the paper: 0.7) */
+    double g[3];          /* gravity; the body force is (rho - rho_b0) g */
+    double s_b, s3, s4, s5, s6; /* relaxation rates of the bulk and higher moments: must be 1 */
+    double grad_eps;      /* |grad phi| <= grad_eps switches perturbation and recolouring term off */
+    /* jet inlet (bc == LBM_BC_JET): circle (x - cx)^2 + (y - cy)^2 < (D/2)^2 at z = -1/2 */
+    double inlet_cx, inlet_cy, inlet_D, inlet_u;
+    double noise_amp;     /* radial inlet velocity noise amplitude, fraction of inlet_u */
+    uint64_t noise_seed;  /* seed of the counter-based SplitMix64 noise */
+    /* droplet preset (init == LBM_INIT_DROPLET): centre, radius, interface width W */
+    double drop_cx, drop_cy, drop_cz, drop_R, drop_W;
+} lbm_params;
+
+/* Byte sizes of the caller-allocated device buffers. */
+typedef struct lbm_sizes {
+    uint64_t n_nodes;
+    uint64_t pop_bytes;     /* each of the two population buffers (A and B) */
+    uint64_t field_bytes;   /* phi, rho - rho_b0 and rho_r/rho: 3 floats per node */
+    uint64_t hist_bytes;    /* outlet plane of the previous step, 54 floats per (x, y); jet only */
+    uint64_t audit_bytes;   /* FP64 partial sums of the audit reduction */
+    uint64_t inlet_bytes;   /* optional inlet axial-velocity profile, nx*ny floats */
+    uint64_t adjoint_bytes; /* adjoint work buffer (see lbm_adjoint_step) */
+    uint64_t state_bytes;   /* a full FP32 state: 54 floats per node (fr[27], fb[27]) */
+} lbm_sizes;
+
+/* Device buffers owned by the caller; must stay valid until lbm_destroy(). */
+typedef struct lbm_buffers {
+    void* pop_a;             /* pop_bytes, 256-byte aligned */
+    void* pop_b;             /* pop_bytes, 256-byte aligned */
+    float* fields;           /* field_bytes */
+    float* hist;             /* hist_bytes; may be NULL when bc == LBM_BC_PERIODIC */
+    double* audit;           /* audit_bytes */
+    const float* inlet_uz;   /* NULL: uniform inlet_u; else nx*ny axial velocities (x fastest) */
+    void* adjoint;           /* adjoint_bytes, or NULL if lbm_adjoint_step is never called */
+} lbm_buffers;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Fill *out with the buffer sizes for p.  Validates p (LBM_ERR_INVALID_ARG /
+ * LBM_ERR_UNSUPPORTED as lbm_init). */
+int lbm_query_sizes(const lbm_params* p, lbm_sizes* out);
+
+/* Create a handle and write the initial state (time t = 0) into buf->pop_a.
+ * With p->init == LBM_INIT_FIELDS the populations are the per-colour
+ * equilibria f_i^k = rho_k {varphi_i(alpha_k) + w_i [velocity terms of
+ * Eq. EES]} of the device fields rho_r[n], rho_b[n] and u[3n..3n+2] (float,
+ * node order; u may be NULL for rest).  The presets ignore the three field
+ * pointers: the droplet of Sec. III (rho_k = rho_k0/2 [1 -/+ tanh(2(r-R)/W)])
+ * or the all-blue jet domain at rest.  Validation rejects nu <= 0,
+ * rho0 <= 0, alpha_b outside (0, 1), alpha_r outside [0, 1), beta outside
+ * [0, 1], rates s_b..s6 != 1 (LBM_ERR_UNSUPPORTED), a jet lattice smaller
+ * than 3 in any dimension or an inlet circle that touches the side walls,
+ * NULL or misaligned buffers.  Writes *h = NULL on failure. */
+int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf,
+             const float* rho_r, const float* rho_b, const float* u, void* hip_stream);
+
+/* Enqueue n_steps full time steps.  Never synchronises the host. */
+int lbm_step(lbm_handle* h, int32_t n_steps);
+
+/* Macroscopic fields of the current state into caller device arrays (each may
+ * be NULL): rho_r[n], rho_b[n], u[3n + a] with the F/2 term of Eq. Momentum,
+ * phi[n] (Eq. order).  If audit (HOST pointer, 5 doubles) is not NULL the
+ * call also computes the FP64 totals sum rho_r, sum rho_b, sum rho u_x,
+ * sum rho u_y, sum rho u_z, synchronises the stream, and returns
+ * LBM_ERR_NONFINITE if any total is not finite. */
+int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* phi,
+                    double* audit);
+
+/* Copy the current state (time lbm_time()) into a device array of
+ * state_bytes: fr[i*N + n] for i < 27, then fb[i*N + n]. */
+int lbm_get_state(lbm_handle* h, float* state);
+
+/* Replace the current state by a device array in the lbm_get_state layout
+ * and set the time level to t (the inlet noise depends on it).  For the jet
+ * the outlet history becomes the outlet plane of this state. */
+int lbm_set_state(lbm_handle* h, const float* state, int64_t t);
+
+/* Time level of the current state (number of steps since init or the t of
+ * the last lbm_set_state). */
+int64_t lbm_time(const lbm_handle* h);
+
+/* One reverse (adjoint) step.  state_t (device, lbm_get_state layout) is the
+ * forward state at time t; lambda (device, same layout) holds on entry the
+ * adjoint of the state at t+1 and on return the adjoint at t.  dJ_dA (device,
+ * 1 double) and dJ_du_in (device, nx*ny floats, may be NULL) are incremented
+ * by this step's contribution to the gradients with respect to A and to the
+ * inlet axial-velocity profile.  Uses buf->adjoint as work space and leaves
+ * the forward state of the handle untouched.  FP32 storage only. */
+int lbm_adjoint_step(lbm_handle* h, const float* state_t, float* lambda, double* dJ_dA,
+                     float* dJ_du_in);
+
+/* Instrumentation: with enable != 0, lbm_step records HIP events on its
+ * stream around each of its two kernels (density pass, fused
+ * collide-recolour-stream kernel); enable == 0 stops recording. */
+int lbm_profile(lbm_handle* h, int enable);
+
+/* Synchronise on the last recorded event, return the summed kernel time in
+ * milliseconds and the launch count since the last read for the density pass
+ * (index 0) and the fused kernel (index 1), and clear them. */
+int lbm_profile_read(lbm_handle* h, double* ms /* 2 */, int64_t* launches /* 2 */);
+
+/* Release the handle (not the caller's buffers).  NULL is accepted. */
+int lbm_destroy(lbm_handle* h);
+
+/* Static description of a status code. */
+const char* lbm_status_string(int status);
+
+/* Thread-local message of the last failure in this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGLBM_H */

@@ -1,0 +1,392 @@
+// C ABI of liblbm.so (declared in include/cglbm.h): validation, buffer
+// sizing, handle state and kernel launches.  Device memory is owned by the
+// caller; this file never allocates it.
+#include <stdarg.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "lbm_adjoint.h"
+#include "lbm_kernels.h"
+
+using namespace cglbm;
+
+struct lbm_handle {
+    lbm_params p;
+    KP k;
+    void* pop[2];
+    int cur;            // buffer holding the current state
+    float* fields;
+    float* hist;
+    double* audit;
+    void* adjoint;
+    hipStream_t stream;
+    long long t;        // time level of the current state
+    int unshifted;      // current buffer holds the pre-collision state itself
+    int nblk;           // blocks of BLOCK threads covering the lattice
+    dim3 grid;          // (ceil(nx*ny / BLOCK), nz)
+    // instrumentation: events around the two kernels of each step
+    int profiling;
+    std::vector<hipEvent_t> ev;  // pool, 3 per recorded step
+    size_t ev_used;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_CHECK(expr)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_bytes(int storage) { return storage == LBM_STORAGE_FP32 ? 4 : 2; }
+
+int validate(const lbm_params* p)
+{
+    if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
+    if (p->bc != LBM_BC_PERIODIC && p->bc != LBM_BC_JET) return fail(LBM_ERR_INVALID_ARG, "unknown bc %d", p->bc);
+    if (p->storage < LBM_STORAGE_FP32 || p->storage > LBM_STORAGE_FP16)
+        return fail(LBM_ERR_INVALID_ARG, "unknown storage %d", p->storage);
+    const int minn = p->bc == LBM_BC_JET ? 3 : 1;
+    if (p->nx < minn || p->ny < minn || p->nz < minn)
+        return fail(LBM_ERR_INVALID_ARG, "lattice %dx%dx%d too small (min %d)", p->nx, p->ny, p->nz, minn);
+    const double nn = (double)p->nx * p->ny * p->nz;
+    if (nn * 8.0 > 4294967295.0) return fail(LBM_ERR_UNSUPPORTED, "more than 2^29 nodes");
+    if (p->nz > 65535) return fail(LBM_ERR_UNSUPPORTED, "nz above 65535");
+    if (!(p->nu_r > 0) || !(p->nu_b > 0)) return fail(LBM_ERR_INVALID_ARG, "viscosities must be > 0");
+    if (!(p->rho_r0 > 0) || !(p->rho_b0 > 0)) return fail(LBM_ERR_INVALID_ARG, "reference densities must be > 0");
+    if (!(p->alpha_b > 0 && p->alpha_b < 1)) return fail(LBM_ERR_INVALID_ARG, "alpha_b must lie in (0, 1)");
+    const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
+    if (!(ar >= 0 && ar < 1)) return fail(LBM_ERR_INVALID_ARG, "alpha_r = %g outside [0, 1)", ar);
+    if (!(p->beta >= 0 && p->beta <= 1)) return fail(LBM_ERR_INVALID_ARG, "beta must lie in [0, 1]");
+    if (!std::isfinite(p->A) || !std::isfinite(p->g[0]) || !std::isfinite(p->g[1]) || !std::isfinite(p->g[2]))
+        return fail(LBM_ERR_INVALID_ARG, "A and g must be finite");
+    if (p->s_b != 1.0 || p->s3 != 1.0 || p->s4 != 1.0 || p->s5 != 1.0 || p->s6 != 1.0)
+        return fail(LBM_ERR_UNSUPPORTED, "only s2b = s3 = s4 = s5 = s6 = 1 (the paper's rates) are implemented");
+    if (!(p->grad_eps >= 0)) return fail(LBM_ERR_INVALID_ARG, "grad_eps must be >= 0");
+    if (p->init < LBM_INIT_FIELDS || p->init > LBM_INIT_JET) return fail(LBM_ERR_INVALID_ARG, "unknown init %d", p->init);
+    if (p->bc == LBM_BC_JET) {
+        if (!(p->inlet_D >= 0) || !std::isfinite(p->inlet_u) || !(p->noise_amp >= 0))
+            return fail(LBM_ERR_INVALID_ARG, "bad inlet parameters");
+    }
+    if (p->init == LBM_INIT_DROPLET && !(p->drop_W > 0))
+        return fail(LBM_ERR_INVALID_ARG, "droplet interface width must be > 0");
+    return LBM_OK;
+}
+
+void fill_kp(const lbm_params* p, const float* inlet, KP* k)
+{
+    k->nx = p->nx;
+    k->ny = p->ny;
+    k->nz = p->nz;
+    k->plane = p->nx * p->ny;
+    k->N = k->plane * p->nz;
+    // p / nx = (p * m) >> (31 + L) with L = ceil(log2 nx), m = ceil(2^(31+L) / nx):
+    // exact for p < 2^31 and m < 2^32
+    int L = 0;
+    while ((1u << L) < (unsigned)p->nx) ++L;
+    const unsigned long long two = 1ull << (31 + L);
+    k->nx_mul = (uint32_t)((two + (unsigned long long)p->nx - 1) / (unsigned long long)p->nx);
+    k->nx_sh = 31 + L;
+    const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
+    k->rho_r0 = (float)p->rho_r0;
+    k->rho_b0 = (float)p->rho_b0;
+    k->alpha_r = (float)ar;
+    k->alpha_b = (float)p->alpha_b;
+    k->dalpha = (float)(ar - p->alpha_b);
+    k->a_minus_w0 = (float)(p->alpha_b - 8.0 / 27.0);
+    k->kappa_b_m1 = (float)(27.0 * (1.0 - p->alpha_b) / 19.0 - 1.0);
+    k->inv_nu_r = (float)(1.0 / p->nu_r);
+    k->inv_nu_b = (float)(1.0 / p->nu_b);
+    k->A = (float)p->A;
+    k->beta = (float)p->beta;
+    k->eps2 = (float)(p->grad_eps * p->grad_eps);
+    k->gx = (float)p->g[0];
+    k->gy = (float)p->g[1];
+    k->gz = (float)p->g[2];
+    k->inlet_cx = (float)p->inlet_cx;
+    k->inlet_cy = (float)p->inlet_cy;
+    k->inlet_r2 = (float)(0.25 * p->inlet_D * p->inlet_D);
+    k->inlet_u = (float)p->inlet_u;
+    k->noise_amp = (float)p->noise_amp;
+    k->seed = p->noise_seed;
+    k->t = 0;
+    k->unshifted = 1;
+    k->inlet_uz = inlet;
+}
+
+template <int V>
+struct IntC {
+    static constexpr int value = V;
+};
+
+// call f(IntC<bc>, Storage) for the handle's configuration
+template <class F>
+int dispatch(int bc, int storage, F&& f)
+{
+    if (bc == LBM_BC_PERIODIC) {
+        if (storage == LBM_STORAGE_FP32) return f(IntC<LBM_BC_PERIODIC>{}, StF32{});
+        if (storage == LBM_STORAGE_BF16) return f(IntC<LBM_BC_PERIODIC>{}, StBF16{});
+        return f(IntC<LBM_BC_PERIODIC>{}, StF16{});
+    }
+    if (storage == LBM_STORAGE_FP32) return f(IntC<LBM_BC_JET>{}, StF32{});
+    if (storage == LBM_STORAGE_BF16) return f(IntC<LBM_BC_JET>{}, StBF16{});
+    return f(IntC<LBM_BC_JET>{}, StF16{});
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
+{
+    int rc = validate(p);
+    if (rc != LBM_OK) return rc;
+    if (!out) return fail(LBM_ERR_INVALID_ARG, "sizes is NULL");
+    const uint64_t N = (uint64_t)p->nx * p->ny * p->nz;
+    const uint64_t plane = (uint64_t)p->nx * p->ny;
+    const uint64_t nblk = ((plane + BLOCK - 1) / BLOCK) * (uint64_t)p->nz;
+    out->n_nodes = N;
+    out->pop_bytes = 2ull * Q * N * elem_bytes(p->storage);
+    out->field_bytes = 3ull * N * sizeof(float);
+    out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * Q * plane * sizeof(float) : 0;
+    out->audit_bytes = (nblk + 1) * 5 * sizeof(double);
+    out->inlet_bytes = plane * sizeof(float);
+    out->adjoint_bytes = adjoint_work_bytes(N);
+    out->state_bytes = 2ull * Q * N * sizeof(float);
+    return LBM_OK;
+}
+
+int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const float* rho_r,
+             const float* rho_b, const float* u, void* hip_stream)
+{
+    if (!h) return fail(LBM_ERR_INVALID_ARG, "handle pointer is NULL");
+    *h = nullptr;
+    int rc = validate(p);
+    if (rc != LBM_OK) return rc;
+    if (!buf || !buf->pop_a || !buf->pop_b || !buf->fields || !buf->audit)
+        return fail(LBM_ERR_INVALID_ARG, "population, field and audit buffers are required");
+    if (p->bc == LBM_BC_JET && !buf->hist) return fail(LBM_ERR_INVALID_ARG, "the jet needs the outlet history buffer");
+    if (!aligned(buf->pop_a, 256) || !aligned(buf->pop_b, 256) || !aligned(buf->fields, 16) ||
+        !aligned(buf->audit, 8) || (buf->hist && !aligned(buf->hist, 16)))
+        return fail(LBM_ERR_INVALID_ARG, "misaligned buffer");
+    if (buf->pop_a == buf->pop_b) return fail(LBM_ERR_INVALID_ARG, "population buffers must differ");
+    if (p->init == LBM_INIT_FIELDS && (!rho_r || !rho_b))
+        return fail(LBM_ERR_INVALID_ARG, "init from fields needs rho_r and rho_b");
+    lbm_handle* H = new (std::nothrow) lbm_handle();
+    if (!H) return fail(LBM_ERR_INVALID_ARG, "out of host memory");
+    H->p = *p;
+    fill_kp(p, buf->inlet_uz, &H->k);
+    H->pop[0] = buf->pop_a;
+    H->pop[1] = buf->pop_b;
+    H->cur = 0;
+    H->fields = buf->fields;
+    H->hist = p->bc == LBM_BC_JET ? buf->hist : nullptr;
+    H->audit = buf->audit;
+    H->adjoint = buf->adjoint;
+    H->stream = (hipStream_t)hip_stream;
+    H->t = 0;
+    H->unshifted = 1;
+    H->grid = dim3((H->k.plane + BLOCK - 1) / BLOCK, p->nz);
+    H->nblk = (int)(H->grid.x * H->grid.y);
+    rc = dispatch(p->bc, p->storage, [&](auto bc, auto st) -> int {
+        using S = decltype(st);
+        (void)bc;
+        const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
+        hipLaunchKernelGGL(k_init<S>, H->grid, dim3(BLOCK), 0, H->stream, (typename S::T*)H->pop[0], H->hist,
+                           H->k, p->init, rho_r, rho_b, u, p->drop_cx, p->drop_cy, p->drop_cz, p->drop_R,
+                           p->drop_W, p->rho_r0, p->rho_b0, ar, p->alpha_b);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    });
+    if (rc != LBM_OK) {
+        delete H;
+        return rc;
+    }
+    *h = H;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int32_t n_steps)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (n_steps < 0) return fail(LBM_ERR_INVALID_ARG, "n_steps < 0");
+    return dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
+        using S = decltype(st);
+        constexpr int BC = decltype(bc)::value;
+        for (int s = 0; s < n_steps; ++s) {
+            h->k.t = h->t;
+            h->k.unshifted = h->unshifted;
+            const typename S::T* src = (const typename S::T*)h->pop[h->cur];
+            typename S::T* dst = (typename S::T*)h->pop[h->cur ^ 1];
+            hipEvent_t* e = nullptr;
+            if (h->profiling) {
+                while (h->ev.size() < h->ev_used + 3) {
+                    hipEvent_t x;
+                    HIP_CHECK(hipEventCreate(&x));
+                    h->ev.push_back(x);
+                }
+                e = &h->ev[h->ev_used];
+                h->ev_used += 3;
+                HIP_CHECK(hipEventRecord(e[0], h->stream));
+            }
+            hipLaunchKernelGGL((k_density<BC, S>), h->grid, dim3(BLOCK), 0, h->stream, src, h->fields,
+                               h->hist, h->k);
+            LAUNCH_CHECK();
+            if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
+            hipLaunchKernelGGL((k_collide<BC, S>), h->grid, dim3(BLOCK), 0, h->stream, src, dst,
+                               h->fields, h->hist, h->k);
+            LAUNCH_CHECK();
+            if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
+            h->cur ^= 1;
+            h->t += 1;
+            h->unshifted = 0;
+        }
+        h->k.t = h->t;
+        h->k.unshifted = h->unshifted;
+        return LBM_OK;
+    });
+}
+
+int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* phi, double* audit)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    h->k.t = h->t;
+    h->k.unshifted = h->unshifted;
+    int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
+        using S = decltype(st);
+        constexpr int BC = decltype(bc)::value;
+        hipLaunchKernelGGL((k_macro<BC, S>), h->grid, dim3(BLOCK), 0, h->stream,
+                           (const typename S::T*)h->pop[h->cur], h->hist, h->k, rho_r, rho_b, u, phi,
+                           audit ? h->audit : nullptr);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    });
+    if (rc != LBM_OK || !audit) return rc;
+    double* tot = h->audit + (size_t)h->nblk * 5;
+    hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, h->stream, h->audit, h->nblk, tot);
+    LAUNCH_CHECK();
+    HIP_CHECK(hipMemcpyAsync(audit, tot, 5 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_CHECK(hipStreamSynchronize(h->stream));
+    for (int a = 0; a < 5; ++a)
+        if (!std::isfinite(audit[a])) return fail(LBM_ERR_NONFINITE, "audit total %d is not finite", a);
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_handle* h, float* state)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (!state) return fail(LBM_ERR_INVALID_ARG, "state is NULL");
+    h->k.t = h->t;
+    h->k.unshifted = h->unshifted;
+    return dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
+        using S = decltype(st);
+        constexpr int BC = decltype(bc)::value;
+        hipLaunchKernelGGL((k_get_state<BC, S>), h->grid, dim3(BLOCK), 0, h->stream,
+                           (const typename S::T*)h->pop[h->cur], h->hist, h->k, state, h->p.rho_b0);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    });
+}
+
+int lbm_set_state(lbm_handle* h, const float* state, int64_t t)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (!state) return fail(LBM_ERR_INVALID_ARG, "state is NULL");
+    if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
+    int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
+        using S = decltype(st);
+        (void)bc;
+        hipLaunchKernelGGL(k_set_state<S>, h->grid, dim3(BLOCK), 0, h->stream,
+                           (typename S::T*)h->pop[h->cur], h->hist, h->k, state, h->p.rho_b0);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    });
+    if (rc != LBM_OK) return rc;
+    h->t = t;
+    h->unshifted = 1;
+    h->k.t = t;
+    h->k.unshifted = 1;
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_handle* h) { return h ? (int64_t)h->t : -1; }
+
+int lbm_adjoint_step(lbm_handle* h, const float* state_t, float* lambda, double* dJ_dA, float* dJ_du_in)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    return adjoint_step(h->p, h->k, h->stream, h->adjoint, h->nblk, state_t, lambda, dJ_dA, dJ_du_in, g_err,
+                        sizeof(g_err));
+}
+
+int lbm_profile(lbm_handle* h, int enable)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    h->profiling = enable != 0;
+    return LBM_OK;
+}
+
+int lbm_profile_read(lbm_handle* h, double* ms, int64_t* launches)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (!ms || !launches) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
+    ms[0] = ms[1] = 0.0;
+    launches[0] = launches[1] = 0;
+    if (h->ev_used) HIP_CHECK(hipEventSynchronize(h->ev[h->ev_used - 1]));
+    for (size_t i = 0; i + 3 <= h->ev_used; i += 3) {
+        float a = 0.f, b = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&a, h->ev[i], h->ev[i + 1]));
+        HIP_CHECK(hipEventElapsedTime(&b, h->ev[i + 1], h->ev[i + 2]));
+        ms[0] += a;
+        ms[1] += b;
+        launches[0] += 1;
+        launches[1] += 1;
+    }
+    h->ev_used = 0;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_handle* h)
+{
+    if (h)
+        for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return LBM_OK;
+}
+
+const char* lbm_status_string(int status)
+{
+    switch (status) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_ERR_INVALID_ARG: return "LBM_ERR_INVALID_ARG: invalid argument";
+    case LBM_ERR_UNSUPPORTED: return "LBM_ERR_UNSUPPORTED: not implemented by this library";
+    case LBM_ERR_HIP: return "LBM_ERR_HIP: HIP runtime error";
+    case LBM_ERR_NONFINITE: return "LBM_ERR_NONFINITE: non-finite audit total";
+    case LBM_ERR_STATE: return "LBM_ERR_STATE: call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char* lbm_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/cglbm.h declares, sizes buffers and validates."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1804_08923_amd import lbm
+from paper_1804_08923_amd.workloads import WORKLOADS, droplet_small, jet_128
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cglbm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(lbm_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_1804_08923_amd.build import build
+        build()
+    return lbm.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(lbm.EXPORTS)
+    assert len(names) == 13
+
+
+def test_query_sizes(lib):
+    for name, mk in WORKLOADS.items():
+        prob = mk()
+        s = lbm.lbm_query_sizes(lbm.make_params(prob))
+        N = prob.n_nodes
+        assert s.n_nodes == N
+        assert s.pop_bytes == 54 * N * 4
+        assert s.state_bytes == 54 * N * 4
+        assert s.field_bytes == 12 * N
+        assert s.hist_bytes == (54 * prob.nx * prob.ny * 4 if prob.bc == "jet" else 0)
+        for st, b in (("bf16", 2), ("fp16", 2)):
+            assert lbm.lbm_query_sizes(lbm.make_params(prob.replace(storage=st))).pop_bytes == 54 * N * b
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nu_r", 0.0, -1), ("nu_b", -1.0, -1), ("rho_b0", 0.0, -1), ("alpha_b", 1.0, -1),
+    ("beta", 1.5, -1), ("s4", 0.9, -2), ("nx", 0, -1), ("bc", 7, -1), ("storage", 9, -1),
+])
+def test_validation(lib, field, value, code):
+    p = lbm.make_params(droplet_small())
+    setattr(p, field, value)
+    s = lbm.lbm_sizes()
+    assert lib.lbm_query_sizes(C.byref(p), C.byref(s)) == code
+    assert lib.lbm_last_error().decode() != ""
+
+
+def test_alpha_r_range(lib):
+    # gamma < 1 - alpha_b makes alpha_r negative
+    p = lbm.make_params(droplet_small().replace(rho_r0=0.5, rho_b0=1.0))
+    s = lbm.lbm_sizes()
+    assert lib.lbm_query_sizes(C.byref(p), C.byref(s)) == -1
+
+
+def test_jet_minimum_size(lib):
+    p = lbm.make_params(jet_128().replace(nz=2))
+    s = lbm.lbm_sizes()
+    assert lib.lbm_query_sizes(C.byref(p), C.byref(s)) == -1
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.lbm_status_string(code).decode().startswith("LBM_")
+
+
+def test_null_handle_is_rejected(lib):
+    assert lib.lbm_step(None, 1) == -5
+    assert lib.lbm_destroy(None) == 0
+    assert lib.lbm_time(None) == -1

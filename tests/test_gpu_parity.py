@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Element-by-element comparisons on seeded inputs at sizes the oracle finishes
+in seconds (several 256-node blocks plus a ragged tail).  Tolerances: the
+spec bar rel L-inf <= 1e-5 on density and velocity after 200 steps of
+the 32^3 droplet; single steps are compared population by population.
+"""
+import numpy as np
+import pytest
+
+from harness import (Q, gpu_fields, oracle_fields, oracle_init, random_state, rel_linf, say,
+                     state_to_f32)
+from oracle import make_params as or_params
+from paper_1804_08923_amd.workloads import Problem, droplet_cm, droplet_small
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible ROCm device"
+    return t
+
+
+def _sim(prob, **kw):
+    from paper_1804_08923_amd.lbm import LBM
+    return LBM(prob, **kw)
+
+
+def _gpu_state(sim):
+    st = sim.get_state().cpu().numpy().astype(np.float64)
+    return st[:Q], st[Q:]
+
+
+def _periodic_random_problem(nx, ny, nz, **kw):
+    base = dict(name="rand", nx=nx, ny=ny, nz=nz, bc="periodic", rho_r0=1.0, rho_b0=0.5,
+                nu_r=0.02, nu_b=0.05, A=2e-3, g=(1e-4, -2e-4, 3e-4), init="jet")
+    base.update(kw)
+    return Problem(**base)
+
+
+@pytest.mark.parametrize("shape", [(16, 12, 10), (13, 7, 5), (32, 32, 1)])
+def test_single_step_random_state(torch, orc, shape):
+    """One step from a random physical state (tau != 1, gamma = 2, eta != 1, g != 0):
+    every population of both colours against the oracle."""
+    prob = _periodic_random_problem(*shape)
+    say(f"single step {shape}")
+    p, fr, fb, h = random_state(orc, prob, seed=sum(shape))
+    st, fr64, fb64 = state_to_f32(fr, fb)
+    sim = _sim(prob)
+    sim.set_state(torch.from_numpy(st).cuda(), t=0)
+    # the state is taken over up to the FP32 rounding of d = f - w rho_b0
+    # (blue is recovered as (d + w rho_b0) - f^r: a few ulps of max |f|)
+    g0r, g0b = _gpu_state(sim)
+    fmax = np.abs(fr64 + fb64).max()
+    assert np.abs(g0r - fr64).max() == 0.0
+    assert np.abs(g0b - fb64).max() <= 4 * 2.0 ** -23 * fmax
+    sim.step(1)
+    gr, gb = _gpu_state(sim)
+    orc.step(p, prob.A, fr64, fb64, np.zeros((2 * Q, p.nx * p.ny)), 0, 1)
+    scale = np.abs(fr64 + fb64).max()
+    err_r = np.abs(gr - fr64).max() / scale
+    err_b = np.abs(gb - fb64).max() / scale
+    say(f"  pop err red {err_r:.2e} blue {err_b:.2e}")
+    assert err_r < 2e-6 and err_b < 2e-6
+    fo = oracle_fields(orc, p, fr64, fb64)
+    fg = gpu_fields(sim)
+    errs = {k: rel_linf(fg[k], fo[k]) for k in ("rho", "u", "phi")}
+    say(f"  rel Linf {errs}")
+    # the FP32 input state is converted to (d, f^r) once (one rounding of d)
+    for k, e in errs.items():
+        assert e < 1e-5, k
+
+
+def _internal_state(sim, prob):
+    """The GPU's stored state right after set_state (unshifted): d_i = f_i - w_i rho_b0
+    and f^r_i in FP32, converted exactly to (fr, fb) in FP64 for the oracle."""
+    from harness import Q as _Q
+    N = prob.n_nodes
+    raw = sim.pop_a.view(torch_mod().float32)[: 2 * _Q * N].reshape(2 * _Q, N).cpu().numpy().astype(np.float64)
+    from oracle import Oracle
+    _, w = Oracle("f64").lattice()
+    d, fr = raw[:_Q], raw[_Q:]
+    fb = d + w[:, None] * prob.rho_b0 - fr
+    return fr.copy(), fb
+
+
+def torch_mod():
+    import torch as t
+    return t
+
+
+@pytest.mark.parametrize("gz", [0.0, 3e-4])
+def test_single_step_exact_state(torch, orc, gz):
+    """One step from exactly the state the GPU holds (no input rounding): velocity,
+    density and order parameter agree to FP32 round-off of the step itself."""
+    prob = _periodic_random_problem(16, 12, 10, g=(1e-4, -2e-4, gz))
+    p, fr, fb, h = random_state(orc, prob, seed=5)
+    st, _, _ = state_to_f32(fr, fb)
+    sim = _sim(prob)
+    sim.set_state(torch.from_numpy(st).cuda(), t=0)
+    fr64, fb64 = _internal_state(sim, prob)
+    sim.step(1)
+    orc.step(p, prob.A, fr64, fb64, np.zeros((2 * Q, p.nx * p.ny)), 0, 1)
+    fo = oracle_fields(orc, p, fr64, fb64)
+    fg = gpu_fields(sim)
+    errs = {k: rel_linf(fg[k], fo[k]) for k in ("rho", "u", "phi", "rho_r")}
+    say(f"  exact-state g_z={gz}: rel Linf {errs}")
+    for k, tol in (("rho", 1e-6), ("u", 1e-6), ("phi", 2e-6), ("rho_r", 2e-6)):
+        assert errs[k] < tol, k
+
+
+def test_droplet_init_matches(torch, orc):
+    prob = droplet_small()
+    sim = _sim(prob)
+    p, fr, fb, h = oracle_init(orc, prob)
+    gr, gb = _gpu_state(sim)
+    assert np.abs(gr - fr).max() < 1e-6 and np.abs(gb - fb).max() < 1e-6
+
+
+# rel L-inf bars after 200 steps.  The 32^3 droplet carries the stated 1e-5 on
+# density and velocity.  The tau != 1, gamma = 2, gravity variant is not a stated
+# configuration: running the FP64 oracle with its state rounded to the FP32
+# (d, f^r) storage after every step already moves u by 1.3e-5, so its velocity
+# bar is set from that storage floor (x 8).
+BARS = {"droplet-32": {"rho": 1e-5, "u": 1e-5, "phi": 1e-5, "rho_r": 1e-5},
+        "droplet-32-cm": {"rho": 1e-5, "u": 1e-4, "phi": 1e-5, "rho_r": 1e-5}}
+
+
+@pytest.mark.parametrize("mk", [droplet_small, droplet_cm])
+def test_droplet_200_steps(torch, orc, mk):
+    """The 32^3 droplet (tau = 1) and its tau != 1, gamma = 2, gravity variant
+    after 200 steps against the oracle."""
+    prob = mk()
+    say(f"droplet {prob.name} {prob.steps} steps")
+    sim = _sim(prob)
+    sim.step(prob.steps)
+    fg = gpu_fields(sim)
+    p, fr, fb, h = oracle_init(orc, prob)
+    orc.step(p, prob.A, fr, fb, h, 0, prob.steps)
+    fo = oracle_fields(orc, p, fr, fb)
+    errs = {k: rel_linf(fg[k], fo[k]) for k in ("rho", "u", "phi", "rho_r")}
+    for k, e in errs.items():
+        say(f"  {k} rel Linf {e:.3e}  (max |{k}| = {np.abs(fo[k]).max():.3e})")
+    for k, e in errs.items():
+        assert e <= BARS[prob.name][k], k
+
+
+def test_periodic_audit_conserves(torch):
+    """FP64 audit: per-colour mass and momentum conserved on a periodic box with g = 0."""
+    prob = droplet_cm().replace(g=(0.0, 0.0, 0.0))
+    sim = _sim(prob)
+    a0 = sim.macroscopic(audit=True)["audit"]
+    sim.step(100)
+    a1 = sim.macroscopic(audit=True)["audit"]
+    say(f"audit {a0} -> {a1}")
+    assert abs(a1[0] - a0[0]) < 1e-5 * a0[0]
+    assert abs(a1[1] - a0[1]) < 1e-5 * a0[1]
+    assert max(abs(a1[k] - a0[k]) for k in (2, 3, 4)) < 1e-6
+
+
+def _small_jet(**kw):
+    from paper_1804_08923_amd.workloads import jet_problem
+    prob = jet_problem("jet-small", 20, 18, 40, D=8, u=0.04, gamma=2.0, eta=1.0, Re=40.0, We=20.0,
+                       Fr=2.0, steps=150, noise_amp=0.01, noise_seed=7)
+    return prob.replace(**kw)
+
+
+@pytest.mark.parametrize("steps", [1, 150])
+def test_small_jet(torch, orc, steps):
+    """Jet boundaries (inflow ghost with seeded noise, free-slip walls,
+    convective outflow) and buoyancy on a 20x18x40 lattice."""
+    prob = _small_jet()
+    say(f"small jet {steps} steps")
+    sim = _sim(prob)
+    sim.step(steps)
+    fg = gpu_fields(sim)
+    p, fr, fb, h = oracle_init(orc, prob)
+    orc.step(p, prob.A, fr, fb, h, 0, steps)
+    fo = oracle_fields(orc, p, fr, fb)
+    errs = {k: rel_linf(fg[k], fo[k]) for k in ("rho", "u", "phi", "rho_r")}
+    say(f"  rel Linf {errs}")
+    for k, e in errs.items():
+        assert e <= 1e-5, k
+    gr, gb = _gpu_state(sim)
+    scale = np.abs(fr + fb).max()
+    assert np.abs(gr - fr).max() / scale < 1e-5
+    assert np.abs(gb - fb).max() / scale < 1e-5
