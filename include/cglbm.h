@@ -55,7 +55,8 @@ enum lbm_init_kind {
 
 /* Problem parameters in lattice units (c = delta_x = delta_t = 1). */
 typedef struct lbm_params {
-    int32_t nx, ny, nz;   /* lattice size; periodic: >= 1 each; jet: >= 3 each; nz <= 65535; at most 2^29 nodes */
+    int32_t nx, ny, nz;   /* lattice size; periodic: >= 1 each; jet: >= 3 each; each <= 65535;
+                             (nx+2)(ny+2)(nz+2) < 2^28 */
     int32_t bc;           /* enum lbm_bc */
     int32_t storage;      /* enum lbm_storage: population storage format */
     int32_t init;         /* enum lbm_init_kind used by lbm_init */
@@ -78,9 +79,11 @@ typedef struct lbm_params {
 /* Byte sizes of the caller-allocated device buffers. */
 typedef struct lbm_sizes {
     uint64_t n_nodes;
-    uint64_t pop_bytes;     /* each of the two population buffers (A and B) */
-    uint64_t field_bytes;   /* phi, rho - rho_b0 and rho_r/rho: 3 floats per node */
-    uint64_t hist_bytes;    /* outlet plane of the previous step, 54 floats per (x, y); jet only */
+    uint64_t pop_bytes;     /* each of the two population buffers (A and B): 54 planes of
+                               (nx+2)(ny+2)(nz+2) padded nodes in the storage format */
+    uint64_t field_bytes;   /* per-node fields and recolouring scalars: 11 floats per padded node */
+    uint64_t hist_bytes;    /* outlet planes of the previous and current step, 2 x 54 floats
+                               per (x, y); jet only */
     uint64_t audit_bytes;   /* FP64 partial sums of the audit reduction */
     uint64_t inlet_bytes;   /* optional inlet axial-velocity profile, nx*ny floats */
     uint64_t adjoint_bytes; /* adjoint work buffer (see lbm_adjoint_step) */
@@ -91,7 +94,7 @@ typedef struct lbm_sizes {
 typedef struct lbm_buffers {
     void* pop_a;             /* pop_bytes, 256-byte aligned */
     void* pop_b;             /* pop_bytes, 256-byte aligned */
-    float* fields;           /* field_bytes */
+    float* fields;           /* field_bytes, 16-byte aligned */
     float* hist;             /* hist_bytes; may be NULL when bc == LBM_BC_PERIODIC */
     double* audit;           /* audit_bytes */
     const float* inlet_uz;   /* NULL: uniform inlet_u; else nx*ny axial velocities (x fastest) */
@@ -154,14 +157,16 @@ int lbm_adjoint_step(lbm_handle* h, const float* state_t, float* lambda, double*
                      float* dJ_du_in);
 
 /* Instrumentation: with enable != 0, lbm_step records HIP events on its
- * stream around each of its two kernels (density pass, fused
- * collide-recolour-stream kernel); enable == 0 stops recording. */
+ * stream around its kernel groups (density pass; fused collide-recolour-
+ * stream kernel; boundary kernels: jet outlet plane and ghost-shell fills);
+ * enable == 0 stops recording. */
 int lbm_profile(lbm_handle* h, int enable);
 
-/* Synchronise on the last recorded event, return the summed kernel time in
- * milliseconds and the launch count since the last read for the density pass
- * (index 0) and the fused kernel (index 1), and clear them. */
-int lbm_profile_read(lbm_handle* h, double* ms /* 2 */, int64_t* launches /* 2 */);
+/* Synchronise on the last recorded event, return the summed time in
+ * milliseconds and the number of recorded steps since the last read for the
+ * density pass (index 0), the fused kernel (index 1) and the boundary kernels
+ * (index 2), and clear them. */
+int lbm_profile_read(lbm_handle* h, double* ms /* 3 */, int64_t* launches /* 3 */);
 
 /* Release the handle (not the caller's buffers).  NULL is accepted. */
 int lbm_destroy(lbm_handle* h);

@@ -16,19 +16,26 @@ struct lbm_handle {
     lbm_params p;
     KP k;
     void* pop[2];
-    int cur;            // buffer holding the current state
-    float* fields;
-    float* hist;
+    int cur;            // population buffer holding the current state
+    float4* R[2];       // (rho_r/rho, V) written together with pop[0] resp. pop[1]
+    float2* PD;         // (phi, rho - rho_b0) per padded node
+    float* XR;          // rho_r / rho per padded node
+    float* hist[2];     // outlet plane (jet): [hprev] previous step, [hprev ^ 1] current
+    int hprev;
     double* audit;
     void* adjoint;
     hipStream_t stream;
     long long t;        // time level of the current state
-    int unshifted;      // current buffer holds the pre-collision state itself
-    int nblk;           // blocks of BLOCK threads covering the lattice
-    dim3 grid;          // (ceil(nx*ny / BLOCK), nz)
-    // instrumentation: events around the two kernels of each step
+    int unshifted;      // current buffer holds a general state at the node itself
+    dim3 grid_all;      // every interior plane
+    dim3 grid_bulk;     // planes handled by the bulk kernels (jet: without the outlet plane)
+    dim3 grid_plane;    // one plane
+    dim3 grid_shell;    // ghost shell cells
+    uint32_t ncells;    // ghost shell cell count
+    int nblk;           // blocks of grid_all (audit partial slots)
+    // instrumentation: events around the kernel groups of each step
     int profiling;
-    std::vector<hipEvent_t> ev;  // pool, 3 per recorded step
+    std::vector<hipEvent_t> ev;  // pool, 5 per recorded step
     size_t ev_used;
 };
 
@@ -59,6 +66,11 @@ int fail(int code, const char* fmt, ...)
 
 size_t elem_bytes(int storage) { return storage == LBM_STORAGE_FP32 ? 4 : 2; }
 
+uint64_t padded_nodes(const lbm_params* p)
+{
+    return (uint64_t)(p->nx + 2) * (uint64_t)(p->ny + 2) * (uint64_t)(p->nz + 2);
+}
+
 int validate(const lbm_params* p)
 {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
@@ -68,9 +80,11 @@ int validate(const lbm_params* p)
     const int minn = p->bc == LBM_BC_JET ? 3 : 1;
     if (p->nx < minn || p->ny < minn || p->nz < minn)
         return fail(LBM_ERR_INVALID_ARG, "lattice %dx%dx%d too small (min %d)", p->nx, p->ny, p->nz, minn);
-    const double nn = (double)p->nx * p->ny * p->nz;
-    if (nn * 8.0 > 4294967295.0) return fail(LBM_ERR_UNSUPPORTED, "more than 2^29 nodes");
-    if (p->nz > 65535) return fail(LBM_ERR_UNSUPPORTED, "nz above 65535");
+    if (p->nx > 65535 || p->ny > 65535 || p->nz > 65535)
+        return fail(LBM_ERR_UNSUPPORTED, "a lattice dimension above 65535");
+    // 32-bit byte offsets of a float4 per padded node
+    if ((double)padded_nodes(p) * 16.0 > 4294967295.0)
+        return fail(LBM_ERR_UNSUPPORTED, "more than 2^28 padded nodes");
     if (!(p->nu_r > 0) || !(p->nu_b > 0)) return fail(LBM_ERR_INVALID_ARG, "viscosities must be > 0");
     if (!(p->rho_r0 > 0) || !(p->rho_b0 > 0)) return fail(LBM_ERR_INVALID_ARG, "reference densities must be > 0");
     if (!(p->alpha_b > 0 && p->alpha_b < 1)) return fail(LBM_ERR_INVALID_ARG, "alpha_b must lie in (0, 1)");
@@ -97,8 +111,11 @@ void fill_kp(const lbm_params* p, const float* inlet, KP* k)
     k->nx = p->nx;
     k->ny = p->ny;
     k->nz = p->nz;
-    k->plane = p->nx * p->ny;
-    k->N = k->plane * p->nz;
+    k->px = p->nx + 2;
+    k->py = p->ny + 2;
+    k->NP = (uint32_t)padded_nodes(p);
+    k->plane = (uint32_t)p->nx * (uint32_t)p->ny;
+    k->N = k->plane * (uint32_t)p->nz;
     // p / nx = (p * m) >> (31 + L) with L = ceil(log2 nx), m = ceil(2^(31+L) / nx):
     // exact for p < 2^31 and m < 2^32
     int L = 0;
@@ -106,6 +123,7 @@ void fill_kp(const lbm_params* p, const float* inlet, KP* k)
     const unsigned long long two = 1ull << (31 + L);
     k->nx_mul = (uint32_t)((two + (unsigned long long)p->nx - 1) / (unsigned long long)p->nx);
     k->nx_sh = 31 + L;
+    k->z0 = 0;
     const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
     k->rho_r0 = (float)p->rho_r0;
     k->rho_b0 = (float)p->rho_b0;
@@ -131,6 +149,7 @@ void fill_kp(const lbm_params* p, const float* inlet, KP* k)
     k->t = 0;
     k->unshifted = 1;
     k->inlet_uz = inlet;
+    k->R = nullptr;
 }
 
 template <int V>
@@ -154,6 +173,17 @@ int dispatch(int bc, int storage, F&& f)
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
+// parameters for reading the current state
+KP read_kp(const lbm_handle* h)
+{
+    KP k = h->k;
+    k.t = h->t;
+    k.unshifted = h->unshifted;
+    k.R = h->R[h->cur];
+    k.z0 = 0;
+    return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -164,12 +194,13 @@ int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
     if (rc != LBM_OK) return rc;
     if (!out) return fail(LBM_ERR_INVALID_ARG, "sizes is NULL");
     const uint64_t N = (uint64_t)p->nx * p->ny * p->nz;
+    const uint64_t NP = padded_nodes(p);
     const uint64_t plane = (uint64_t)p->nx * p->ny;
     const uint64_t nblk = ((plane + BLOCK - 1) / BLOCK) * (uint64_t)p->nz;
     out->n_nodes = N;
-    out->pop_bytes = 2ull * Q * N * elem_bytes(p->storage);
-    out->field_bytes = 3ull * N * sizeof(float);
-    out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * Q * plane * sizeof(float) : 0;
+    out->pop_bytes = 2ull * Q * NP * elem_bytes(p->storage);
+    out->field_bytes = 11ull * NP * sizeof(float);
+    out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * 2ull * Q * plane * sizeof(float) : 0;
     out->audit_bytes = (nblk + 1) * 5 * sizeof(double);
     out->inlet_bytes = plane * sizeof(float);
     out->adjoint_bytes = adjoint_work_bytes(N);
@@ -197,25 +228,38 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     if (!H) return fail(LBM_ERR_INVALID_ARG, "out of host memory");
     H->p = *p;
     fill_kp(p, buf->inlet_uz, &H->k);
+    const size_t NP = H->k.NP;
     H->pop[0] = buf->pop_a;
     H->pop[1] = buf->pop_b;
     H->cur = 0;
-    H->fields = buf->fields;
-    H->hist = p->bc == LBM_BC_JET ? buf->hist : nullptr;
+    H->R[0] = (float4*)buf->fields;
+    H->R[1] = (float4*)(buf->fields + 4 * NP);
+    H->PD = (float2*)(buf->fields + 8 * NP);
+    H->XR = buf->fields + 10 * NP;
+    const size_t hplane = 2 * (size_t)Q * H->k.plane;
+    H->hist[0] = p->bc == LBM_BC_JET ? buf->hist : nullptr;
+    H->hist[1] = p->bc == LBM_BC_JET ? buf->hist + hplane : nullptr;
+    H->hprev = 0;
     H->audit = buf->audit;
     H->adjoint = buf->adjoint;
     H->stream = (hipStream_t)hip_stream;
     H->t = 0;
     H->unshifted = 1;
-    H->grid = dim3((H->k.plane + BLOCK - 1) / BLOCK, p->nz);
-    H->nblk = (int)(H->grid.x * H->grid.y);
+    const unsigned bx = (H->k.plane + BLOCK - 1) / BLOCK;
+    H->grid_all = dim3(bx, p->nz);
+    H->grid_bulk = dim3(bx, p->bc == LBM_BC_JET ? p->nz - 1 : p->nz);
+    H->grid_plane = dim3(bx, 1);
+    const uint64_t cells = 2ull * H->k.px * H->k.py + 2ull * H->k.px * p->nz + 2ull * p->ny * p->nz;
+    H->ncells = (uint32_t)cells;
+    H->grid_shell = dim3((unsigned)((cells + BLOCK - 1) / BLOCK));
+    H->nblk = (int)(H->grid_all.x * H->grid_all.y);
     rc = dispatch(p->bc, p->storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         (void)bc;
         const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
-        hipLaunchKernelGGL(k_init<S>, H->grid, dim3(BLOCK), 0, H->stream, (typename S::T*)H->pop[0], H->hist,
-                           H->k, p->init, rho_r, rho_b, u, p->drop_cx, p->drop_cy, p->drop_cz, p->drop_R,
-                           p->drop_W, p->rho_r0, p->rho_b0, ar, p->alpha_b);
+        hipLaunchKernelGGL(k_init<S>, H->grid_all, dim3(BLOCK), 0, H->stream, (typename S::T*)H->pop[0], H->k,
+                           p->init, rho_r, rho_b, u, p->drop_cx, p->drop_cy, p->drop_cz, p->drop_R, p->drop_W,
+                           p->rho_r0, p->rho_b0, ar, p->alpha_b, (double)H->k.rho_b0);
         LAUNCH_CHECK();
         return LBM_OK;
     });
@@ -233,37 +277,60 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
     if (n_steps < 0) return fail(LBM_ERR_INVALID_ARG, "n_steps < 0");
     return dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
+        using T = typename S::T;
         constexpr int BC = decltype(bc)::value;
+        constexpr bool jet = BC == LBM_BC_JET;
         for (int s = 0; s < n_steps; ++s) {
-            h->k.t = h->t;
-            h->k.unshifted = h->unshifted;
-            const typename S::T* src = (const typename S::T*)h->pop[h->cur];
-            typename S::T* dst = (typename S::T*)h->pop[h->cur ^ 1];
+            KP k = read_kp(h);
+            KP ko = k;
+            ko.z0 = h->p.nz - 1;
+            const T* src = (const T*)h->pop[h->cur];
+            T* dst = (T*)h->pop[h->cur ^ 1];
+            float4* Rout = h->R[h->cur ^ 1];
+            float* hprev = h->hist[h->hprev];
+            float* hcur = h->hist[h->hprev ^ 1];
             hipEvent_t* e = nullptr;
             if (h->profiling) {
-                while (h->ev.size() < h->ev_used + 3) {
+                while (h->ev.size() < h->ev_used + 5) {
                     hipEvent_t x;
                     HIP_CHECK(hipEventCreate(&x));
                     h->ev.push_back(x);
                 }
                 e = &h->ev[h->ev_used];
-                h->ev_used += 3;
+                h->ev_used += 5;
                 HIP_CHECK(hipEventRecord(e[0], h->stream));
             }
-            hipLaunchKernelGGL((k_density<BC, S>), h->grid, dim3(BLOCK), 0, h->stream, src, h->fields,
-                               h->hist, h->k);
+            // density pass
+            hipLaunchKernelGGL(k_density<S>, h->grid_bulk, dim3(BLOCK), 0, h->stream, src, h->PD, h->XR, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
-            hipLaunchKernelGGL((k_collide<BC, S>), h->grid, dim3(BLOCK), 0, h->stream, src, dst,
-                               h->fields, h->hist, h->k);
+            if (jet) {
+                hipLaunchKernelGGL(k_outlet_density<S>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->PD,
+                                   h->XR, hprev, hcur, ko);
+                LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
+            // fused collide-perturb-recolour-stream
+            hipLaunchKernelGGL((k_collide<BC, S>), h->grid_bulk, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,
+                               Rout, k);
+            LAUNCH_CHECK();
+            if (e) HIP_CHECK(hipEventRecord(e[3], h->stream));
+            if (jet) {
+                hipLaunchKernelGGL(k_outlet_collide<S>, h->grid_plane, dim3(BLOCK), 0, h->stream, hcur, dst, h->PD,
+                                   h->XR, Rout, ko);
+                LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL((k_pop_ghosts<BC, S>), h->grid_shell, dim3(BLOCK), 0, h->stream, dst, Rout, k,
+                               h->ncells);
+            LAUNCH_CHECK();
+            if (e) HIP_CHECK(hipEventRecord(e[4], h->stream));
             h->cur ^= 1;
+            if (jet) h->hprev ^= 1;
             h->t += 1;
             h->unshifted = 0;
         }
-        h->k.t = h->t;
-        h->k.unshifted = h->unshifted;
         return LBM_OK;
     });
 }
@@ -271,13 +338,12 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
 int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* phi, double* audit)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
-    h->k.t = h->t;
-    h->k.unshifted = h->unshifted;
+    const KP k = read_kp(h);
     int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         constexpr int BC = decltype(bc)::value;
-        hipLaunchKernelGGL((k_macro<BC, S>), h->grid, dim3(BLOCK), 0, h->stream,
-                           (const typename S::T*)h->pop[h->cur], h->hist, h->k, rho_r, rho_b, u, phi,
+        hipLaunchKernelGGL((k_macro<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                           (const typename S::T*)h->pop[h->cur], h->hist[h->hprev], k, rho_r, rho_b, u, phi,
                            audit ? h->audit : nullptr);
         LAUNCH_CHECK();
         return LBM_OK;
@@ -297,13 +363,12 @@ int lbm_get_state(lbm_handle* h, float* state)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
     if (!state) return fail(LBM_ERR_INVALID_ARG, "state is NULL");
-    h->k.t = h->t;
-    h->k.unshifted = h->unshifted;
+    const KP k = read_kp(h);
     return dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         constexpr int BC = decltype(bc)::value;
-        hipLaunchKernelGGL((k_get_state<BC, S>), h->grid, dim3(BLOCK), 0, h->stream,
-                           (const typename S::T*)h->pop[h->cur], h->hist, h->k, state, h->p.rho_b0);
+        hipLaunchKernelGGL((k_get_state<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                           (const typename S::T*)h->pop[h->cur], h->hist[h->hprev], k, state, (double)h->k.rho_b0);
         LAUNCH_CHECK();
         return LBM_OK;
     });
@@ -314,19 +379,18 @@ int lbm_set_state(lbm_handle* h, const float* state, int64_t t)
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
     if (!state) return fail(LBM_ERR_INVALID_ARG, "state is NULL");
     if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
+    const KP k = read_kp(h);
     int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         (void)bc;
-        hipLaunchKernelGGL(k_set_state<S>, h->grid, dim3(BLOCK), 0, h->stream,
-                           (typename S::T*)h->pop[h->cur], h->hist, h->k, state, h->p.rho_b0);
+        hipLaunchKernelGGL(k_set_state<S>, h->grid_all, dim3(BLOCK), 0, h->stream, (typename S::T*)h->pop[h->cur],
+                           k, state, (double)h->k.rho_b0);
         LAUNCH_CHECK();
         return LBM_OK;
     });
     if (rc != LBM_OK) return rc;
     h->t = t;
     h->unshifted = 1;
-    h->k.t = t;
-    h->k.unshifted = 1;
     return LBM_OK;
 }
 
@@ -350,17 +414,21 @@ int lbm_profile_read(lbm_handle* h, double* ms, int64_t* launches)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
     if (!ms || !launches) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
-    ms[0] = ms[1] = 0.0;
-    launches[0] = launches[1] = 0;
+    ms[0] = ms[1] = ms[2] = 0.0;
+    launches[0] = launches[1] = launches[2] = 0;
     if (h->ev_used) HIP_CHECK(hipEventSynchronize(h->ev[h->ev_used - 1]));
-    for (size_t i = 0; i + 3 <= h->ev_used; i += 3) {
-        float a = 0.f, b = 0.f;
+    for (size_t i = 0; i + 5 <= h->ev_used; i += 5) {
+        float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
         HIP_CHECK(hipEventElapsedTime(&a, h->ev[i], h->ev[i + 1]));
         HIP_CHECK(hipEventElapsedTime(&b, h->ev[i + 1], h->ev[i + 2]));
+        HIP_CHECK(hipEventElapsedTime(&c, h->ev[i + 2], h->ev[i + 3]));
+        HIP_CHECK(hipEventElapsedTime(&d, h->ev[i + 3], h->ev[i + 4]));
         ms[0] += a;
-        ms[1] += b;
+        ms[1] += c;
+        ms[2] += b + d;
         launches[0] += 1;
         launches[1] += 1;
+        launches[2] += 1;
     }
     h->ev_used = 0;
     return LBM_OK;

@@ -1,26 +1,35 @@
 // HIP kernels of the colour-gradient D3Q27 central-moment LBM step for gfx950.
 //
 // Design (one MI355X, one process):
-//  * State: two population buffers (A-B), structure of arrays, 54 planes of
-//    N nodes: planes 0..26 hold the colour-blind deviation d_i = f_i - w_i rho_b0,
-//    planes 27..53 the red populations f^r_i; blue is f_i - f^r_i.  d is small
-//    in both pure phases (rho_r0 varphi_i(alpha_r) = rho_b0 w_i for |c_i| >= 1
-//    because gamma = (1 - alpha_b)/(1 - alpha_r)), so FP32 and 16-bit storage
-//    keep the momentum sum_i d_i c_i well conditioned.
-//  * Pull streaming: a buffer holds post-collision values at their source
-//    node; the pre-collision value of direction i at x is read from x - c_i,
-//    and the jet boundary rules are applied at that read.  Right after
-//    initialisation the buffer holds the pre-collision state itself
-//    ("unshifted"), read without a shift.
-//  * A step is two kernels: the density pass (writes phi, rho - rho_b0 and
-//    rho_r/rho per node) and the fused collide-perturb-recolour-stream
-//    kernel, which reads only the 27 colour-blind deviations (the red
-//    populations enter only through rho_r/rho), the 27-point stencil of
-//    (phi, rho - rho_b0) and writes all 54 post-collision values.
-//  * Launch geometry: grid (ceil(nx*ny/256), nz), so z = blockIdx.y is uniform
-//    per block and, when nx is a multiple of 64, y is uniform per wavefront;
-//    the z and y boundary branches are then taken by whole wavefronts.  Loads
-//    and stores use a uniform plane base plus a 32-bit byte offset.
+//  * Lattice storage is padded by one ghost cell on every side: padded strides
+//    px = nx + 2, py = ny + 2, and nz + 2 planes; interior node (x, y, z) sits
+//    at ((z + 1) py + y + 1) px + x + 1.  After each pass a small kernel writes
+//    into the ghost shell what the boundary rules demand (periodic copies;
+//    for the jet, free-slip mirror images, inlet equilibria inside the inlet
+//    circle), so the interior kernels pull with one uniform offset per
+//    direction and no branches.
+//  * Populations: A-B buffers, structure of arrays, planes of NP padded nodes.
+//    Planes 0..26 hold the colour-blind deviation d_i = f_i - w_i rho_b0; d is
+//    small in both pure phases (rho_r0 varphi_i(alpha_r) = rho_b0 w_i for
+//    |c_i| >= 1 because gamma = (1 - alpha_b)/(1 - alpha_r)), so FP32 and
+//    16-bit storage keep the momentum sum_i d_i c_i well conditioned.
+//  * Red populations: after recolouring (Eqs. op3r/op3b) with
+//    varphi_i = w_i kappa(alpha_bar) for |c_i| >= 1 and cos(theta_i) linear in
+//    c_i, the red post-collision populations are
+//        f^r*_i = (rho_r/rho) f'_i + (w_i / |c_i|) c_i . V,
+//        V = beta (rho_r rho_b / rho) kappa grad phi / |grad phi|,
+//    an affine function of the colour-blind post-collision f' with four
+//    per-node scalars.  The fused kernel therefore stores only d' and the
+//    float4 R = (rho_r/rho, V) of every node; readers rebuild f^r of direction
+//    i at x from d_i and R at the source node x - c_i.  A general state (after
+//    initialisation or set_state) keeps the red populations in planes 27..53
+//    at the node itself ("unshifted") and is read that way by the first step.
+//  * A step: density pass (phi, rho - rho_b0, rho_r/rho per node), ghost fill
+//    of those fields, fused collide-perturb-recolour-stream kernel (reads 27
+//    deviations and the (phi, rho) stencil, writes 27 deviations and R), ghost
+//    fill of the populations.  The jet outlet plane z = nz - 1 (convective
+//    condition) has its own density and collision kernels.
+//  * Launch geometry: grid (ceil(nx*ny/256), planes), z = blockIdx.y + z0.
 //  * Collision: with s0 = s1 = 0 and s2b = s3..s6 = 1 (Sec. II) the GMRT
 //    collision (Eq. scoll) leaves every central moment at its equilibrium
 //    value plus half the forcing moment, except the five deviatoric second-
@@ -70,9 +79,14 @@ struct StF16 {
 
 // ---------------------------------------------------------------- parameters
 struct KP {
-    int nx, ny, nz, N, plane;
+    int nx, ny, nz;    // interior lattice
+    int px, py;        // padded strides: nx + 2, ny + 2
+    uint32_t NP;       // padded node count px * py * (nz + 2)
+    uint32_t N;        // interior node count nx * ny * nz
+    uint32_t plane;    // nx * ny
     uint32_t nx_mul;   // p / nx = (p * nx_mul) >> nx_sh, exact for p < 2^31
     int nx_sh;
+    int z0;            // interior plane of blockIdx.y = 0
     float rho_r0, rho_b0, alpha_r, alpha_b;
     float dalpha;      // alpha_r - alpha_b
     float a_minus_w0;  // alpha_b - w_0
@@ -82,14 +96,40 @@ struct KP {
     float inlet_cx, inlet_cy, inlet_r2, inlet_u, noise_amp;
     uint64_t seed;
     long long t;       // time level of the state that is read
-    int unshifted;     // state stored without the streaming shift
+    int unshifted;     // general state (54 planes) stored without the streaming shift
     const float* inlet_uz;
+    const float4* R;   // (rho_r/rho, V) of the post-collision state that is read
 };
 
-// node coordinates of this thread: z = blockIdx.y, planar index p
+struct MirrorTable {
+    int8_t v[Q * 8];
+};
+constexpr MirrorTable make_mirror()
+{
+    MirrorTable t{};
+    for (int i = 0; i < Q; ++i)
+        for (int m = 0; m < 8; ++m) t.v[i * 8 + m] = (int8_t)mirror_dir(i, m);
+    return t;
+}
+// direction i with the components in mask m (bit 0: x, 1: y, 2: z) reversed
+__constant__ MirrorTable kMirror = make_mirror();
+
+__device__ __forceinline__ uint32_t pidx(const KP& k, int x, int y, int z)
+{
+    return ((uint32_t)(z + 1) * (uint32_t)k.py + (uint32_t)(y + 1)) * (uint32_t)k.px + (uint32_t)(x + 1);
+}
+
+// padded-index offset of lattice velocity (cx, cy, cz)
+__device__ __forceinline__ int doff(const KP& k, int cx, int cy, int cz)
+{
+    return cx + cy * k.px + cz * k.px * k.py;
+}
+
+// interior node of this thread: z = blockIdx.y + z0
 struct Node {
     int x, y, z;
-    uint32_t n;
+    uint32_t n;  // padded index
+    uint32_t q;  // y nx + x (index within an interior plane)
     bool valid;
 };
 
@@ -97,11 +137,12 @@ __device__ __forceinline__ Node this_node(const KP& k)
 {
     Node d;
     const uint32_t p = blockIdx.x * 256u + threadIdx.x;
-    d.valid = p < (uint32_t)k.plane;
-    d.z = blockIdx.y;
+    d.valid = p < k.plane;
+    d.z = (int)blockIdx.y + k.z0;
     d.y = (int)(((uint64_t)p * k.nx_mul) >> k.nx_sh);
     d.x = (int)p - d.y * k.nx;
-    d.n = (uint32_t)d.z * (uint32_t)k.plane + p;
+    d.q = p;
+    d.n = pidx(k, d.x, d.y, d.z);
     return d;
 }
 
@@ -154,101 +195,70 @@ __device__ __forceinline__ float inlet_feq_dir(const KP& k, int xg, int yg, long
     return k.rho_r0 * wgt(I) * (kap_r + poly);  // |c_I| >= 1 here: varphi_I = w_I kappa_r
 }
 
-// ---------------------------------------------------------------- pull with boundary rules
-// value of direction P (compile-time plane) at source s
-template <class S, int P, bool WANT_FR>
-__device__ __forceinline__ void load_pair(const typename S::T* __restrict__ src, size_t N, uint32_t s, float& d,
-                                          float& fr)
-{
-    d = S::dec(ldp(src + (size_t)P * N, s));
-    if (WANT_FR) fr = S::dec(ldp(src + (size_t)(Q + P) * N, s));
-}
-
-// plane of direction I mirrored across the axes in mask M (bit 1: y, bit 2: z)
+// ---------------------------------------------------------------- pull
+// Pre-collision value of direction I at padded node n of a post-collision
+// (shifted) state: d from plane I at n - c_I (an interior node or a filled
+// ghost cell), f^r rebuilt from R there.
 template <class S, int I, bool WANT_FR>
-__device__ __forceinline__ void load_mirrored_yz(const typename S::T* __restrict__ src, size_t N, int m,
-                                                 uint32_t s, float& d, float& fr)
+__device__ __forceinline__ void pull_shifted(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
+                                             float& d, float& fr)
 {
-    switch (m) {
-    case 2: load_pair<S, mirror_dir(I, 2), WANT_FR>(src, N, s, d, fr); break;
-    case 4: load_pair<S, mirror_dir(I, 4), WANT_FR>(src, N, s, d, fr); break;
-    case 6: load_pair<S, mirror_dir(I, 6), WANT_FR>(src, N, s, d, fr); break;
-    default: load_pair<S, I, WANT_FR>(src, N, s, d, fr); break;
+    const uint32_t s = n - (uint32_t)doff(k, kCX[I], kCY[I], kCZ[I]);
+    d = S::dec(ldp(src + (size_t)I * k.NP, s));
+    if (WANT_FR) {
+        const float4 r = ldp(k.R, s);
+        float v = r.x * (d + wgt(I) * k.rho_b0);
+        if (I != 0) v += (wgt(I) * inv_len(I)) * (kCX[I] * r.y + kCY[I] * r.z + kCZ[I] * r.w);
+        fr = v;
     }
 }
 
-// Reads the pre-collision value of direction I at node nd.
-// Periodic: wrap.  Jet: inlet ghost inside the circle at z = -1, specular
-// reflection (free slip) at the half-way walls x, y = -1/2, n - 1/2 and
-// z = -1/2 elsewhere.  The outlet plane z = nz - 1 is handled separately.
-template <int BC, class S, int I, bool WANT_FR>
-__device__ __forceinline__ void pull(const typename S::T* __restrict__ src, size_t N, const KP& k, const Node& nd,
-                                     float& d, float& fr)
+// value of direction I of a general state stored at node n itself
+template <class S, int I, bool WANT_FR>
+__device__ __forceinline__ void pull_general(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
+                                             float& d, float& fr)
 {
-    constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
-    if (k.unshifted) {
-        load_pair<S, I, WANT_FR>(src, N, nd.n, d, fr);
-        return;
-    }
-    int s = (int)nd.n - cx - cy * k.nx - cz * k.plane;
-    if (BC == LBM_BC_PERIODIC) {
-        if (cx > 0 && nd.x == 0) s += k.nx;
-        if (cx < 0 && nd.x == k.nx - 1) s -= k.nx;
-        if (cy > 0 && nd.y == 0) s += k.plane;
-        if (cy < 0 && nd.y == k.ny - 1) s -= k.plane;
-        if (cz > 0 && nd.z == 0) s += k.N;
-        if (cz < 0 && nd.z == k.nz - 1) s -= k.N;
-        load_pair<S, I, WANT_FR>(src, N, (uint32_t)s, d, fr);
-        return;
-    }
-    const bool mz = cz > 0 && nd.z == 0;
-    if (mz && inlet_inside(k, nd.x - cx, nd.y - cy)) {
-        const float fe = inlet_feq_dir<I>(k, nd.x - cx, nd.y - cy, k.t - 1);
-        d = fe - wgt(I) * k.rho_b0;
-        if (WANT_FR) fr = fe;
-        return;
-    }
-    const bool mx = (cx > 0 && nd.x == 0) || (cx < 0 && nd.x == k.nx - 1);
-    const bool my = (cy > 0 && nd.y == 0) || (cy < 0 && nd.y == k.ny - 1);
-    if (mx) s += cx;
-    if (my) s += cy * k.nx;
-    if (mz) s += cz * k.plane;
-    const int myz = (my ? 2 : 0) | (mz ? 4 : 0);
-    if (cy == 0 && cz <= 0)
-        load_pair<S, I, WANT_FR>(src, N, (uint32_t)s, d, fr);
-    else
-        load_mirrored_yz<S, I, WANT_FR>(src, N, myz, (uint32_t)s, d, fr);
-    if (cx != 0 && mx) {
-        switch (myz) {
-        case 2: load_pair<S, mirror_dir(I, 3), WANT_FR>(src, N, (uint32_t)s, d, fr); break;
-        case 4: load_pair<S, mirror_dir(I, 5), WANT_FR>(src, N, (uint32_t)s, d, fr); break;
-        case 6: load_pair<S, mirror_dir(I, 7), WANT_FR>(src, N, (uint32_t)s, d, fr); break;
-        default: load_pair<S, mirror_dir(I, 1), WANT_FR>(src, N, (uint32_t)s, d, fr); break;
-        }
-    }
+    d = S::dec(ldp(src + (size_t)I * k.NP, n));
+    if (WANT_FR) fr = S::dec(ldp(src + (size_t)(Q + I) * k.NP, n));
 }
 
-template <int BC, class S, bool WANT_FR, int I = 0>
-__device__ __forceinline__ void pull_all(const typename S::T* __restrict__ src, size_t N, const KP& k,
-                                         const Node& nd, float* d, float* fr)
+template <class S, bool WANT_FR, bool SHIFTED, int I = 0>
+__device__ __forceinline__ void pull_dirs(const typename S::T* __restrict__ src, const KP& k, uint32_t n, float* d,
+                                          float* fr)
 {
     if constexpr (I < Q) {
-        pull<BC, S, I, WANT_FR>(src, N, k, nd, d[I], fr[I]);
-        pull_all<BC, S, WANT_FR, I + 1>(src, N, k, nd, d, fr);
+        if constexpr (SHIFTED)
+            pull_shifted<S, I, WANT_FR>(src, k, n, d[I], fr[I]);
+        else
+            pull_general<S, I, WANT_FR>(src, k, n, d[I], fr[I]);
+        pull_dirs<S, WANT_FR, SHIFTED, I + 1>(src, k, n, d, fr);
     }
+}
+
+// the 27 pre-collision values (and red populations) at padded node n
+template <class S, bool WANT_FR>
+__device__ __forceinline__ void pull_all(const typename S::T* __restrict__ src, const KP& k, uint32_t n, float* d,
+                                         float* fr)
+{
+    if (k.unshifted)
+        pull_dirs<S, WANT_FR, false>(src, k, n, d, fr);
+    else
+        pull_dirs<S, WANT_FR, true>(src, k, n, d, fr);
 }
 
 // Pre-collision state of an outlet node (x, y, nz - 1) by the convective
 // condition f(N) = [f_prev(N) + lam f(N - 1)] / (1 + lam), lam = max(0, u_z(N - 1))
-// evaluated on the freshly streamed populations of the node below.
+// evaluated on the freshly streamed populations of the node below; hprev holds
+// the outlet plane of the previous step (d, then f^r).
 template <class S>
-__device__ void outlet_state(const typename S::T* __restrict__ src, size_t N, const KP& k,
-                             const float* __restrict__ hist, const Node& nd, float* d, float* fr)
+__device__ void outlet_state(const typename S::T* __restrict__ src, const KP& k, const float* __restrict__ hprev,
+                             const Node& nd, float* d, float* fr)
 {
-    Node nb = nd;
-    nb.z = k.nz - 2;
-    nb.n = nd.n - (uint32_t)k.plane;
-    pull_all<LBM_BC_JET, S, true>(src, N, k, nb, d, fr);
+    if (k.unshifted) {
+        pull_all<S, true>(src, k, nd.n, d, fr);
+        return;
+    }
+    pull_all<S, true>(src, k, nd.n - (uint32_t)(k.px * k.py), d, fr);
     float m0 = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -259,23 +269,22 @@ __device__ void outlet_state(const typename S::T* __restrict__ src, size_t N, co
     const float uz = (jz + 0.5f * m0 * k.gz) / rho;
     const float lam = uz > 0.f ? uz : 0.f;
     const float inv = 1.f / (1.f + lam);
-    const uint32_t q = nd.n - (uint32_t)(k.nz - 1) * (uint32_t)k.plane;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        d[i] = (hist[(size_t)i * k.plane + q] + lam * d[i]) * inv;
-        fr[i] = (hist[(size_t)(Q + i) * k.plane + q] + lam * fr[i]) * inv;
+        d[i] = (hprev[(size_t)i * k.plane + nd.q] + lam * d[i]) * inv;
+        fr[i] = (hprev[(size_t)(Q + i) * k.plane + nd.q] + lam * fr[i]) * inv;
     }
 }
 
-// full pre-collision state (54 values) of any node
+// full pre-collision state (54 values) of any interior node
 template <int BC, class S>
-__device__ __forceinline__ void read_state(const typename S::T* __restrict__ src, size_t N, const KP& k,
-                                           const float* __restrict__ hist, const Node& nd, float* d, float* fr)
+__device__ __forceinline__ void read_state(const typename S::T* __restrict__ src, const KP& k,
+                                           const float* __restrict__ hprev, const Node& nd, float* d, float* fr)
 {
-    if (BC == LBM_BC_JET && nd.z == k.nz - 1 && !k.unshifted)
-        outlet_state<S>(src, N, k, hist, nd, d, fr);
+    if (BC == LBM_BC_JET && nd.z == k.nz - 1)
+        outlet_state<S>(src, k, hprev, nd, d, fr);
     else
-        pull_all<BC, S, true>(src, N, k, nd, d, fr);
+        pull_all<S, true>(src, k, nd.n, d, fr);
 }
 
 // ---------------------------------------------------------------- block reduction (FP64 audit)
@@ -303,22 +312,13 @@ __device__ void block_partials(double (&v)[NV], double* __restrict__ out, uint32
     }
 }
 
-// ---------------------------------------------------------------- kernels
 constexpr int BLOCK = 256;
 
-// Field layout (float): [0, 2N) (phi, rho - rho_b0) pairs per node, [2N, 3N) rho_r / rho.
-
-// Density pass: rho_r = sum f^r, rho - rho_b0 = sum d; phi (Eq. order).
-template <int BC, class S>
-__global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restrict__ src,
-                                                    float* __restrict__ fields,
-                                                    const float* __restrict__ hist, KP k)
+// ---------------------------------------------------------------- density pass
+// fields: PD = (phi, rho - rho_b0) per padded node, XR = rho_r / rho.
+__device__ __forceinline__ void store_fields(float2* __restrict__ PD, float* __restrict__ XR, const KP& k, uint32_t n,
+                                             const float* d, const float* fr)
 {
-    const Node nd = this_node(k);
-    if (!nd.valid) return;
-    const size_t N = (size_t)k.N;
-    float d[Q], fr[Q];
-    read_state<BC, S>(src, N, k, hist, nd, d, fr);
     double m0 = 0.0, rr = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -328,67 +328,288 @@ __global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restri
     const double rho = (double)k.rho_b0 + m0;
     const double rb = rho - rr;
     const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
-    stp((float2*)fields, nd.n, make_float2((float)((a - b) / (a + b)), (float)m0));
-    stp(fields + 2 * N, nd.n, (float)(rr / rho));
+    stp(PD, n, make_float2((float)((a - b) / (a + b)), (float)m0));  // Eq. order
+    stp(XR, n, (float)(rr / rho));
 }
 
-// offset to neighbour x + c with the ghost rules: periodic wrap, or (jet) a
-// mirrored copy (index clamp) at the walls and the outlet ghost plane; returns
-// false where the neighbour is the inlet ghost (phi = 1, rho = rho_r0).
-template <int BC, int CX, int CY, int CZ>
-__device__ __forceinline__ bool neighbour(const KP& k, const Node& nd, int& s)
+__host__ __device__ constexpr double inv_lend(int i)
 {
-    s = (int)nd.n + CX + CY * k.nx + CZ * k.plane;
-    if (BC == LBM_BC_PERIODIC) {
-        if (CX < 0 && nd.x == 0) s += k.nx;
-        if (CX > 0 && nd.x == k.nx - 1) s -= k.nx;
-        if (CY < 0 && nd.y == 0) s += k.plane;
-        if (CY > 0 && nd.y == k.ny - 1) s -= k.plane;
-        if (CZ < 0 && nd.z == 0) s += k.N;
-        if (CZ > 0 && nd.z == k.nz - 1) s -= k.N;
-        return true;
-    }
-    if (CZ < 0 && nd.z == 0) {
-        if (inlet_inside(k, nd.x + CX, nd.y + CY)) return false;
-        s -= CZ * k.plane;
-    }
-    if (CZ > 0 && nd.z == k.nz - 1) s -= CZ * k.plane;
-    if ((CX < 0 && nd.x == 0) || (CX > 0 && nd.x == k.nx - 1)) s -= CX;
-    if ((CY < 0 && nd.y == 0) || (CY > 0 && nd.y == k.ny - 1)) s -= CY * k.nx;
-    return true;
+    return csq(i) == 1 ? 1.0 : csq(i) == 2 ? 0.70710678118654752440 : 0.57735026918962576451;
 }
 
-__host__ __device__ constexpr double wgtd(int i)
-{
-    return csq(i) == 0 ? 8.0 / 27.0 : csq(i) == 1 ? 2.0 / 27.0 : csq(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
-}
-
-template <int BC, int CX, int CY, int CZ>
-__device__ __forceinline__ float2 stencil_value(const float2* __restrict__ pd, const KP& k, const Node& nd)
-{
-    int s;
-    if (neighbour<BC, CX, CY, CZ>(k, nd, s)) return ldp(pd, (uint32_t)s);
-    return make_float2(1.f, k.rho_r0 - k.rho_b0);
-}
-
-// isotropic gradients 3 sum_i w_i chi(x + c_i) c_i of phi and rho - rho_b0,
-// accumulated over opposite pairs (i, i + 1) in FP64: g = (dphi[3], drho[3])
-template <int BC, int I = 1>
-__device__ __forceinline__ void gradients(const float2* __restrict__ pd, const KP& k, const Node& nd,
-                                          double (&g)[6])
+// mass and red mass of the pre-collision state at n, accumulated in FP64 (the
+// red populations of a shifted state rebuilt in FP64 with exact weights)
+template <class S, bool SHIFTED, int I = 0>
+__device__ __forceinline__ void accum_density(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
+                                              double& m0, double& rr)
 {
     if constexpr (I < Q) {
         constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
-        const float2 a = stencil_value<BC, cx, cy, cz>(pd, k, nd);
-        const float2 b = stencil_value<BC, -cx, -cy, -cz>(pd, k, nd);
+        if constexpr (SHIFTED) {
+            const uint32_t s = n - (uint32_t)doff(k, cx, cy, cz);
+            const double d = S::dec(ldp(src + (size_t)I * k.NP, s));
+            const float4 r = ldp(k.R, s);
+            double v = (double)r.x * (d + wgtd(I) * (double)k.rho_b0);
+            if (I != 0) v += (wgtd(I) * inv_lend(I)) * ((double)(cx * r.y) + (double)(cy * r.z) + (double)(cz * r.w));
+            m0 += d;
+            rr += v;
+        } else {
+            m0 += (double)S::dec(ldp(src + (size_t)I * k.NP, n));
+            rr += (double)S::dec(ldp(src + (size_t)(Q + I) * k.NP, n));
+        }
+        accum_density<S, SHIFTED, I + 1>(src, k, n, m0, rr);
+    }
+}
+
+__device__ __forceinline__ void store_fields_sums(float2* __restrict__ PD, float* __restrict__ XR, const KP& k,
+                                                  uint32_t n, double m0, double rr)
+{
+    const double rho = (double)k.rho_b0 + m0;
+    const double rb = rho - rr;
+    const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
+    stp(PD, n, make_float2((float)((a - b) / (a + b)), (float)m0));  // Eq. order
+    stp(XR, n, (float)(rr / rho));
+}
+
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
+                                                    float* __restrict__ XR, KP k)
+{
+    const Node nd = this_node(k);
+    if (!nd.valid) return;
+    double m0 = 0.0, rr = 0.0;
+    if (k.unshifted)
+        accum_density<S, false>(src, k, nd.n, m0, rr);
+    else
+        accum_density<S, true>(src, k, nd.n, m0, rr);
+    store_fields_sums(PD, XR, k, nd.n, m0, rr);
+}
+
+// jet outlet plane: convective condition, records the plane in hcur
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_outlet_density(const typename S::T* __restrict__ src,
+                                                           float2* __restrict__ PD, float* __restrict__ XR,
+                                                           const float* __restrict__ hprev,
+                                                           float* __restrict__ hcur, KP k)
+{
+    const Node nd = this_node(k);
+    if (!nd.valid) return;
+    float d[Q], fr[Q];
+    outlet_state<S>(src, k, hprev, nd, d, fr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        hcur[(size_t)i * k.plane + nd.q] = d[i];
+        hcur[(size_t)(Q + i) * k.plane + nd.q] = fr[i];
+    }
+    store_fields(PD, XR, k, nd.n, d, fr);
+}
+
+// ---------------------------------------------------------------- ghost shell
+// Ghost cell g of the shell: z faces (all x, y incl. ghosts), then y faces
+// (z interior), then x faces (y, z interior).
+struct Ghost {
+    int x, y, z;
+    bool valid;
+};
+
+__device__ __forceinline__ Ghost shell_cell(const KP& k, uint32_t g)
+{
+    Ghost c;
+    const uint32_t A = (uint32_t)k.px * k.py, B = (uint32_t)k.px * k.nz, C = (uint32_t)k.ny * k.nz;
+    c.valid = true;
+    if (g < 2 * A) {
+        const uint32_t f = g / A, r = g - f * A;
+        c.x = (int)(r % k.px) - 1;
+        c.y = (int)(r / k.px) - 1;
+        c.z = f ? k.nz : -1;
+    } else if (g < 2 * A + 2 * B) {
+        const uint32_t h = g - 2 * A, f = h / B, r = h - f * B;
+        c.x = (int)(r % k.px) - 1;
+        c.z = (int)(r / k.px);
+        c.y = f ? k.ny : -1;
+    } else if (g < 2 * A + 2 * B + 2 * C) {
+        const uint32_t h = g - 2 * A - 2 * B, f = h / C, r = h - f * C;
+        c.y = (int)(r % k.ny);
+        c.z = (int)(r / k.ny);
+        c.x = f ? k.nx : -1;
+    } else {
+        c.valid = false;
+        c.x = c.y = c.z = 0;
+    }
+    return c;
+}
+
+__device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+__device__ __forceinline__ int clampc(int a, int n) { return a < 0 ? 0 : (a >= n ? n - 1 : a); }
+
+// (phi, rho - rho_b0) in the shell: periodic copies, or (jet) mirrored copies
+// across the half-way walls and the outlet, and (1, rho_r0 - rho_b0) in the
+// inlet circle at z = -1.
+template <int BC>
+__global__ __launch_bounds__(BLOCK) void k_field_ghosts(float2* __restrict__ PD, KP k, uint32_t ncells)
+{
+    const uint32_t g = blockIdx.x * BLOCK + threadIdx.x;
+    if (g >= ncells) return;
+    const Ghost c = shell_cell(k, g);
+    if (!c.valid) return;
+    const uint32_t dst = pidx(k, c.x, c.y, c.z);
+    if (BC == LBM_BC_PERIODIC) {
+        PD[dst] = PD[pidx(k, wrapc(c.x, k.nx), wrapc(c.y, k.ny), wrapc(c.z, k.nz))];
+        return;
+    }
+    if (c.z < 0 && inlet_inside(k, c.x, c.y)) {
+        PD[dst] = make_float2(1.f, k.rho_r0 - k.rho_b0);
+        return;
+    }
+    PD[dst] = PD[pidx(k, clampc(c.x, k.nx), clampc(c.y, k.ny), clampc(c.z, k.nz))];
+}
+
+// Populations and R in the shell cells the fused kernel does not write: every
+// shell cell except x-face cells with y and z interior.  A ghost cell g feeds
+// direction I of an interior node iff c_I points into the domain along every
+// axis on which g lies outside.  Periodic: copy of the wrapped node.  Jet:
+// specular reflection, the populations of the clamped node with the outside
+// components of c_I reversed and V mirrored alike; inside the inlet circle at
+// z = -1 the red inlet equilibrium (d = f^e - w rho_b0, R = (1, 0, 0, 0)).
+template <int BC, class S, int I = 0>
+__device__ __forceinline__ void ghost_dirs(typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
+                                           uint32_t gi, uint32_t wi, int m, bool inlet)
+{
+    if constexpr (I < Q) {
+        const size_t NP = k.NP;
+        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
+        const bool in = (c.x >= 0 && c.x < k.nx ? true : (c.x < 0 ? cx > 0 : cx < 0)) &&
+                        (c.y >= 0 && c.y < k.ny ? true : (c.y < 0 ? cy > 0 : cy < 0)) &&
+                        (c.z >= 0 && c.z < k.nz ? true : (c.z < 0 ? cz > 0 : cz < 0));
+        if (in) {
+            if (BC == LBM_BC_PERIODIC) {
+                dst[(size_t)I * NP + gi] = dst[(size_t)I * NP + wi];
+            } else if (cz > 0 && inlet) {
+                const float fe = inlet_feq_dir<(cz > 0 ? I : 5)>(k, c.x, c.y, k.t);
+                dst[(size_t)I * NP + gi] = S::enc(fe - wgt(I) * k.rho_b0);
+            } else {
+                const int J = kMirror.v[I * 8 + m];
+                dst[(size_t)I * NP + gi] = dst[(size_t)J * NP + wi];
+            }
+        }
+        ghost_dirs<BC, S, I + 1>(dst, k, c, gi, wi, m, inlet);
+    }
+}
+
+template <int BC, class S>
+__global__ __launch_bounds__(BLOCK) void k_pop_ghosts(typename S::T* __restrict__ dst, float4* __restrict__ Rout,
+                                                       KP k, uint32_t ncells)
+{
+    const uint32_t g = blockIdx.x * BLOCK + threadIdx.x;
+    if (g >= ncells) return;
+    const Ghost c = shell_cell(k, g);
+    if (!c.valid) return;
+    // x-face cells of interior rows: written by the fused kernel
+    if ((c.x < 0 || c.x >= k.nx) && c.y >= 1 && c.y <= k.ny - 2 && c.z >= 1 && c.z <= k.nz - 2) return;
+    if (BC == LBM_BC_JET && c.z >= k.nz) return;  // the outlet plane is never pulled across
+    const uint32_t gi = pidx(k, c.x, c.y, c.z);
+    if (BC == LBM_BC_PERIODIC) {
+        const uint32_t wi = pidx(k, wrapc(c.x, k.nx), wrapc(c.y, k.ny), wrapc(c.z, k.nz));
+        ghost_dirs<BC, S>(dst, k, c, gi, wi, 0, false);
+        Rout[gi] = Rout[wi];
+        return;
+    }
+    const bool inlet = c.z < 0 && inlet_inside(k, c.x, c.y);
+    const int m = ((c.x < 0 || c.x >= k.nx) ? 1 : 0) | ((c.y < 0 || c.y >= k.ny) ? 2 : 0) | (c.z < 0 ? 4 : 0);
+    const uint32_t wi = pidx(k, clampc(c.x, k.nx), clampc(c.y, k.ny), clampc(c.z, k.nz));
+    ghost_dirs<BC, S>(dst, k, c, gi, wi, m, inlet);
+    if (inlet) {
+        Rout[gi] = make_float4(1.f, 0.f, 0.f, 0.f);
+    } else {
+        const float4 r = Rout[wi];
+        Rout[gi] = make_float4(r.x, (m & 1) ? -r.y : r.y, (m & 2) ? -r.z : r.z, (m & 4) ? -r.w : r.w);
+    }
+}
+
+// ---------------------------------------------------------------- stencil
+// isotropic gradients 3 sum_i w_i chi(x + c_i) c_i of phi and rho - rho_b0,
+// accumulated over opposite pairs (i, i + 1) in FP64: g = (dphi[3], drho[3])
+template <int I = 1>
+__device__ __forceinline__ void gradients(const float2* __restrict__ pd, const KP& k, uint32_t n, double (&g)[6])
+{
+    if constexpr (I < Q) {
+        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
+        const int o = doff(k, cx, cy, cz);
+        const float2 a = ldp(pd, n + (uint32_t)o);
+        const float2 b = ldp(pd, n - (uint32_t)o);
         const double dp = (double)a.x - (double)b.x, dr = (double)a.y - (double)b.y;
         constexpr double w3 = 3.0 * wgtd(I);
         if (cx) { g[0] += (w3 * cx) * dp; g[3] += (w3 * cx) * dr; }
         if (cy) { g[1] += (w3 * cy) * dp; g[4] += (w3 * cy) * dr; }
         if (cz) { g[2] += (w3 * cz) * dp; g[5] += (w3 * cz) * dr; }
-        gradients<BC, I + 2>(pd, k, nd, g);
+        gradients<I + 2>(pd, k, n, g);
     }
 }
+
+// ---------------------------------------------------------------- ghost writes of the fused kernel
+// A post-collision population J of a boundary node W that would stream out of
+// the lattice is what some interior node pulls from a ghost cell.  Periodic:
+// the ghost on the opposite side, same direction.  Jet: the ghost W + c_J in the
+// plane of J reversed along the wall normal (specular reflection, free slip).
+// The fused kernel writes the ghosts of x-wall nodes whose y and z are
+// interior (one lane per wavefront, strided cells); k_pop_ghosts fills the
+// rest of the shell afterwards.
+// the common case: the node lies on an x wall only (y and z interior)
+template <int BC, class S, int J>
+__device__ __forceinline__ void ghost_pop_x(const KP& k, const Node& nd, typename S::T* __restrict__ dst, float v,
+                                            bool xl, bool xh)
+{
+    constexpr int cx = kCX[J];
+    if constexpr (cx != 0) {
+        if (cx < 0 ? xl : xh) {
+            if (BC == LBM_BC_PERIODIC)
+                stp(dst + (size_t)J * k.NP, nd.n - (uint32_t)(cx * k.nx), S::enc(v));
+            else
+                stp(dst + (size_t)mirror_dir(J, 1) * k.NP, nd.n + (uint32_t)cx, S::enc(v));
+        }
+    }
+}
+
+// R = (rho_r/rho, V) of the x-wall ghost cell this node feeds: a copy
+// (periodic) or with V_x reversed (free slip)
+template <int BC>
+__device__ __forceinline__ void ghost_R_x(const KP& k, const Node& nd, float4* __restrict__ Rout, float4 r, bool xl,
+                                          bool xh)
+{
+    if (BC == LBM_BC_PERIODIC) {
+        if (xh) stp(Rout, nd.n - (uint32_t)k.nx, r);
+        if (xl) stp(Rout, nd.n + (uint32_t)k.nx, r);
+    } else {
+        const float4 m = make_float4(r.x, -r.y, r.z, r.w);
+        if (xl) stp(Rout, nd.n - 1u, m);
+        if (xh) stp(Rout, nd.n + 1u, m);
+    }
+}
+
+template <int BC, class S, int I>
+__device__ __forceinline__ void ghost_pair_t(const KP& k, const Node& nd, typename S::T* __restrict__ dst, float vp,
+                                             float vm, bool xl, bool xh, bool yz_edge)
+{
+    if (!yz_edge) {
+        ghost_pop_x<BC, S, I>(k, nd, dst, vp, xl, xh);
+        ghost_pop_x<BC, S, I + 1>(k, nd, dst, vm, xl, xh);
+    }
+}
+
+#define CGLBM_GP(I) \
+    case I: ghost_pair_t<BC, S, I>(k, nd, dst, vp, vm, xl, xh, yz_edge); break;
+// dispatch on the (unrolled, constant) pair index
+template <int BC, class S>
+__device__ __forceinline__ void ghost_pair(int i, const KP& k, const Node& nd, typename S::T* __restrict__ dst,
+                                           float vp, float vm, bool xl, bool xh, bool yz_edge)
+{
+    switch (i) {
+        CGLBM_GP(1) CGLBM_GP(3) CGLBM_GP(5) CGLBM_GP(7) CGLBM_GP(9) CGLBM_GP(11) CGLBM_GP(13)
+        CGLBM_GP(15) CGLBM_GP(17) CGLBM_GP(19) CGLBM_GP(21) CGLBM_GP(23) CGLBM_GP(25)
+    default: break;
+    }
+}
+#undef CGLBM_GP
 
 // one-dimensional inverse central-moment basis: for shift u, the vectors
 // h0, h1 (and the constant h2 = (1/2, -1, 1/2)) over c = -1, 0, 1 whose
@@ -409,14 +630,17 @@ __device__ __forceinline__ constexpr float h2(int c) { return c == 0 ? -1.f : 0.
 
 // Collision, perturbation and recolouring of one node from its pre-collision
 // colour-blind deviations d, the centre values phic and xr = rho_r/rho and
-// the gradients; writes the 54 post-collision values to dst at node n.  The
-// scalar part runs in FP64 (cancellation-prone sums and differences), the
-// per-direction part in FP32.
-template <class S>
-__device__ __forceinline__ void collide_store(const KP& k, const float* d, float phic, float xr,
-                                              const double (&g)[6], typename S::T* __restrict__ dst, size_t N,
-                                              uint32_t n)
+// the gradients; writes the 27 post-collision colour-blind deviations to dst
+// and (rho_r/rho, V) of the recolouring to Rout at node n.  The scalar part
+// runs in FP64 (cancellation-prone sums and differences), the per-direction
+// part in FP32.
+template <int BC, class S>
+__device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const float* d, float phic, float xr,
+                                              const double (&g)[6], typename S::T* __restrict__ dst,
+                                              float4* __restrict__ Rout)
 {
+    const size_t N = k.NP;
+    const uint32_t n = nd.n;
     // raw moments of d up to second order
     double m0 = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     double pxx = 0.0, pyy = 0.0, pzz = 0.0, pxy = 0.0, pxz = 0.0, pyz = 0.0;
@@ -497,8 +721,14 @@ __device__ __forceinline__ void collide_store(const KP& k, const float* d, float
     const float gn = on ? sqrtf(G2) : 0.f;
     const float inv_gn = on ? 1.f / gn : 0.f;
     const float Agn = k.A * gn, Aign = k.A * inv_gn;
+    // recolouring vector V = beta (rho_r rho_b / rho) kappa n
     const float rec = k.beta * xr * (1.f - xr) * rhof * (float)kap * inv_gn;
+    const float4 rv = make_float4(xr, rec * gpx, rec * gpy, rec * gpz);
+    stp(Rout, n, rv);
     const float nub9 = 9.f * nubf;
+    const bool xl = nd.x == 0, xh = nd.x == k.nx - 1;
+    const bool yz_edge = nd.y == 0 || nd.y == k.ny - 1 || nd.z == 0 || nd.z == k.nz - 1;
+    if (!yz_edge) ghost_R_x<BC>(k, nd, Rout, rv, xl, xh);
 
     // rest population
     {
@@ -509,7 +739,6 @@ __device__ __forceinline__ void collide_store(const KP& k, const float* d, float
         const float delta = U0[1][1] * bx.h0[1] + U1[1][1] * bx.h1[1] + U2[1][1] * h2(0);
         const float dd = de + 0.5f * Fp + delta + pert;
         stp(dst, n, S::enc(dd));
-        stp(dst + (size_t)Q * N, n, S::enc(xr * (dd + w * k.rho_b0)));
     }
     // opposite pairs (i, i + 1): shared even parts, odd parts change sign
 #pragma unroll
@@ -527,7 +756,6 @@ __device__ __forceinline__ void collide_store(const KP& k, const float* d, float
         const float pert = w * (Aign * cg * cg - Agn);
         const float even = de_e + fp_e + pert;
         const float odd = de_o + fp_o;
-        const float rc = rec * w * inv_len(i) * cg;
         // direction i (+c) and i + 1 (-c)
         const float dl_p = U0[cy + 1][cz + 1] * bx.h0[cx + 1] + U1[cy + 1][cz + 1] * bx.h1[cx + 1]
                            + U2[cy + 1][cz + 1] * h2(cx);
@@ -537,55 +765,63 @@ __device__ __forceinline__ void collide_store(const KP& k, const float* d, float
         const float dm = even - odd + dl_m;
         stp(dst + (size_t)i * N, n, S::enc(dp));
         stp(dst + (size_t)(i + 1) * N, n, S::enc(dm));
-        stp(dst + (size_t)(Q + i) * N, n, S::enc(xr * (dp + w * k.rho_b0) + rc));
-        stp(dst + (size_t)(Q + i + 1) * N, n, S::enc(xr * (dm + w * k.rho_b0) - rc));
+        ghost_pair<BC, S>(i, k, nd, dst, dp, dm, xl, xh, yz_edge);
     }
 }
 
+
+// ---------------------------------------------------------------- fused collide-recolour-stream
 template <int BC, class S>
 __global__ __launch_bounds__(BLOCK) void k_collide(const typename S::T* __restrict__ src,
-                                                    typename S::T* __restrict__ dst,
-                                                    const float* __restrict__ fields,
-                                                    float* __restrict__ hist, KP k)
+                                                    typename S::T* __restrict__ dst, const float2* __restrict__ PD,
+                                                    const float* __restrict__ XR, float4* __restrict__ Rout, KP k)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
-    const size_t N = (size_t)k.N;
-    float d[Q];
-    if (BC == LBM_BC_JET && nd.z == k.nz - 1) {
-        float fr[Q];
-        read_state<BC, S>(src, N, k, hist, nd, d, fr);
-        const uint32_t q = nd.n - (uint32_t)(k.nz - 1) * (uint32_t)k.plane;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            hist[(size_t)i * k.plane + q] = d[i];
-            hist[(size_t)(Q + i) * k.plane + q] = fr[i];
-        }
-    } else {
-        float unused[Q];
-        pull_all<BC, S, false>(src, N, k, nd, d, unused);
-    }
-    const float2* pd = (const float2*)fields;
-    const float phic = ldp(pd, nd.n).x;
-    const float xr = ldp(fields + 2 * N, nd.n);
+    float d[Q], unused[Q];
+    pull_all<S, false>(src, k, nd.n, d, unused);
+    const float phic = ldp(PD, nd.n).x;
+    const float xr = ldp(XR, nd.n);
     double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    gradients<BC>(pd, k, nd, g);
-    collide_store<S>(k, d, phic, xr, g, dst, N, nd.n);
+    gradients(PD, k, nd.n, g);
+    collide_store<BC, S>(k, nd, d, phic, xr, g, dst, Rout);
 }
 
-// Initial state (unshifted): per-colour equilibria f^k_i = rho_k {varphi_i(alpha_k)
-// + w_i [velocity terms of Eq. EES]} of the droplet / jet preset or of caller
-// fields, evaluated in FP64 and rounded once to the storage format.
+// jet outlet plane: the pre-collision state was recorded by k_outlet_density
 template <class S>
-__global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst, float* __restrict__ hist,
-                                                 KP k, int kind, const float* __restrict__ frr,
-                                                 const float* __restrict__ frb, const float* __restrict__ fu,
-                                                 double dcx, double dcy, double dcz, double R, double W,
-                                                 double rho_r0, double rho_b0, double alpha_r, double alpha_b)
+__global__ __launch_bounds__(BLOCK) void k_outlet_collide(const float* __restrict__ hcur,
+                                                           typename S::T* __restrict__ dst,
+                                                           const float2* __restrict__ PD,
+                                                           const float* __restrict__ XR, float4* __restrict__ Rout,
+                                                           KP k)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
-    const size_t N = (size_t)k.N;
+    float d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = hcur[(size_t)i * k.plane + nd.q];
+    const float phic = ldp(PD, nd.n).x;
+    const float xr = ldp(XR, nd.n);
+    double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    gradients(PD, k, nd.n, g);
+    collide_store<LBM_BC_JET, S>(k, nd, d, phic, xr, g, dst, Rout);
+}
+
+// ---------------------------------------------------------------- state in and out
+// Initial state (general form): per-colour equilibria f^k_i = rho_k {varphi_i(alpha_k)
+// + w_i [velocity terms of Eq. EES]} of the droplet / jet preset or of caller
+// fields (node order), evaluated in FP64 and rounded once to the storage format.
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst, KP k, int kind,
+                                                 const float* __restrict__ frr, const float* __restrict__ frb,
+                                                 const float* __restrict__ fu, double dcx, double dcy, double dcz,
+                                                 double R, double W, double rho_r0, double rho_b0, double alpha_r,
+                                                 double alpha_b, double rho_ref)
+{
+    const Node nd = this_node(k);
+    if (!nd.valid) return;
+    const size_t NP = k.NP;
+    const uint32_t u_idx = (uint32_t)nd.z * k.plane + nd.q;
     double rr, rb, ux = 0, uy = 0, uz = 0;
     if (kind == LBM_INIT_DROPLET) {
         const double dx = nd.x - dcx, dy = nd.y - dcy, dz = nd.z - dcz;
@@ -596,21 +832,19 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst,
         rr = 0.0;
         rb = rho_b0;
     } else {
-        rr = frr[nd.n];
-        rb = frb[nd.n];
+        rr = frr[u_idx];
+        rb = frb[u_idx];
         if (fu) {
-            ux = fu[3 * nd.n];
-            uy = fu[3 * nd.n + 1];
-            uz = fu[3 * nd.n + 2];
+            ux = fu[3 * (size_t)u_idx];
+            uy = fu[3 * (size_t)u_idx + 1];
+            uz = fu[3 * (size_t)u_idx + 2];
         }
     }
     const double u2 = ux * ux + uy * uy + uz * uz;
     const double kap_r = 27.0 * (1.0 - alpha_r) / 19.0, kap_b = 27.0 * (1.0 - alpha_b) / 19.0;
-    const uint32_t q = nd.n - (uint32_t)(k.nz - 1) * (uint32_t)k.plane;
-    const bool outlet = hist != nullptr && nd.z == k.nz - 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double w = i == 0 ? 8.0 / 27.0 : csq(i) == 1 ? 2.0 / 27.0 : csq(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+        const double w = wgtd(i);
         const double cu = kCX[i] * ux + kCY[i] * uy + kCZ[i] * uz;
         const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * u2 + 4.5 * cu * cu * cu - 4.5 * cu * u2;
         double fv, fb;
@@ -621,99 +855,85 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst,
             fv = rr * w * (kap_r + poly);
             fb = rb * w * (kap_b + poly);
         }
-        const double dv = (fv + fb) - w * rho_b0;
-        const typename S::T ed = S::enc((float)dv), ef = S::enc((float)fv);
-        stp(dst + (size_t)i * N, nd.n, ed);
-        stp(dst + (size_t)(Q + i) * N, nd.n, ef);
-        if (outlet) {
-            hist[(size_t)i * k.plane + q] = S::dec(ed);
-            hist[(size_t)(Q + i) * k.plane + q] = S::dec(ef);
-        }
+        const double dv = (fv + fb) - w * rho_ref;  // deviation from the kernels' reference density
+        stp(dst + (size_t)i * NP, nd.n, S::enc((float)dv));
+        stp(dst + (size_t)(Q + i) * NP, nd.n, S::enc((float)fv));
     }
 }
 
-// set an explicit (fr, fb) FP32 state, unshifted; d is formed in FP64 and
-// rounded once
+// set an explicit (fr, fb) FP32 state (node order), general form; d is
+// formed in FP64 and rounded once
 template <class S>
-__global__ __launch_bounds__(BLOCK) void k_set_state(typename S::T* __restrict__ dst, float* __restrict__ hist,
-                                                      KP k, const float* __restrict__ st, double rho_b0)
+__global__ __launch_bounds__(BLOCK) void k_set_state(typename S::T* __restrict__ dst, KP k,
+                                                      const float* __restrict__ st, double rho_b0)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
-    const size_t N = (size_t)k.N;
-    const uint32_t q = nd.n - (uint32_t)(k.nz - 1) * (uint32_t)k.plane;
-    const bool outlet = hist != nullptr && nd.z == k.nz - 1;
+    const size_t NP = k.NP, N = k.N;
+    const uint32_t u_idx = (uint32_t)nd.z * k.plane + nd.q;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double w = i == 0 ? 8.0 / 27.0 : csq(i) == 1 ? 2.0 / 27.0 : csq(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
-        const float fr = st[(size_t)i * N + nd.n], fb = st[(size_t)(Q + i) * N + nd.n];
-        const double dv = ((double)fr + (double)fb) - w * rho_b0;
-        const typename S::T ed = S::enc((float)dv), ef = S::enc(fr);
-        stp(dst + (size_t)i * N, nd.n, ed);
-        stp(dst + (size_t)(Q + i) * N, nd.n, ef);
-        if (outlet) {
-            hist[(size_t)i * k.plane + q] = S::dec(ed);
-            hist[(size_t)(Q + i) * k.plane + q] = S::dec(ef);
-        }
+        const float fr = st[(size_t)i * N + u_idx], fb = st[(size_t)(Q + i) * N + u_idx];
+        const double dv = ((double)fr + (double)fb) - wgtd(i) * rho_b0;
+        stp(dst + (size_t)i * NP, nd.n, S::enc((float)dv));
+        stp(dst + (size_t)(Q + i) * NP, nd.n, S::enc(fr));
     }
 }
 
-// current state as (fr, fb) FP32 (blue formed in FP64, rounded once)
+// current state as (fr, fb) FP32 in node order (blue formed in FP64, rounded once)
 template <int BC, class S>
 __global__ __launch_bounds__(BLOCK) void k_get_state(const typename S::T* __restrict__ src,
-                                                      const float* __restrict__ hist, KP k,
-                                                      float* __restrict__ st, double rho_b0)
+                                                      const float* __restrict__ hprev, KP k, float* __restrict__ st,
+                                                      double rho_b0)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
-    const size_t N = (size_t)k.N;
+    const size_t N = k.N;
+    const uint32_t u_idx = (uint32_t)nd.z * k.plane + nd.q;
     float d[Q], fr[Q];
-    read_state<BC, S>(src, N, k, hist, nd, d, fr);
+    read_state<BC, S>(src, k, hprev, nd, d, fr);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double w = i == 0 ? 8.0 / 27.0 : csq(i) == 1 ? 2.0 / 27.0 : csq(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
-        st[(size_t)i * N + nd.n] = fr[i];
-        st[(size_t)(Q + i) * N + nd.n] = (float)(((double)d[i] + w * rho_b0) - (double)fr[i]);
+        st[(size_t)i * N + u_idx] = fr[i];
+        st[(size_t)(Q + i) * N + u_idx] = (float)(((double)d[i] + wgtd(i) * rho_b0) - (double)fr[i]);
     }
 }
 
-// macroscopic fields and FP64 audit partial sums (one slot per block)
+// macroscopic fields (node order) and FP64 audit partial sums (one slot per block)
 template <int BC, class S>
 __global__ __launch_bounds__(BLOCK) void k_macro(const typename S::T* __restrict__ src,
-                                                  const float* __restrict__ hist, KP k,
-                                                  float* __restrict__ o_rr, float* __restrict__ o_rb,
-                                                  float* __restrict__ o_u, float* __restrict__ o_phi,
-                                                  double* __restrict__ partials)
+                                                  const float* __restrict__ hprev, KP k, float* __restrict__ o_rr,
+                                                  float* __restrict__ o_rb, float* __restrict__ o_u,
+                                                  float* __restrict__ o_phi, double* __restrict__ partials)
 {
     const Node nd = this_node(k);
     double acc[5] = {0, 0, 0, 0, 0};
     if (nd.valid) {
-        const size_t N = (size_t)k.N;
         float d[Q], fr[Q];
-        read_state<BC, S>(src, N, k, hist, nd, d, fr);
-        float m0 = 0.f, rr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+        read_state<BC, S>(src, k, hprev, nd, d, fr);
+        double m0 = 0.0, rr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            m0 += d[i];
-            rr += fr[i];
-            if (kCX[i]) jx += kCX[i] * d[i];
-            if (kCY[i]) jy += kCY[i] * d[i];
-            if (kCZ[i]) jz += kCZ[i] * d[i];
+            m0 += (double)d[i];
+            rr += (double)fr[i];
+            if (kCX[i]) jx += kCX[i] * (double)d[i];
+            if (kCY[i]) jy += kCY[i] * (double)d[i];
+            if (kCZ[i]) jz += kCZ[i] * (double)d[i];
         }
-        const float rho = k.rho_b0 + m0;
-        const float rb = rho - rr;
-        const float px = jx + 0.5f * m0 * k.gx, py = jy + 0.5f * m0 * k.gy, pz = jz + 0.5f * m0 * k.gz;
-        const uint32_t n = nd.n;
-        if (o_rr) o_rr[n] = rr;
-        if (o_rb) o_rb[n] = rb;
+        const double rho = (double)k.rho_b0 + m0;
+        const double rb = rho - rr;
+        const double px = jx + 0.5 * m0 * k.gx, py = jy + 0.5 * m0 * k.gy, pz = jz + 0.5 * m0 * k.gz;
+        const size_t n = (size_t)nd.z * k.plane + nd.q;
+        if (o_rr) o_rr[n] = (float)rr;
+        if (o_rb) o_rb[n] = (float)rb;
         if (o_u) {
-            o_u[3 * (size_t)n] = px / rho;
-            o_u[3 * (size_t)n + 1] = py / rho;
-            o_u[3 * (size_t)n + 2] = pz / rho;
+            o_u[3 * n] = (float)(px / rho);
+            o_u[3 * n + 1] = (float)(py / rho);
+            o_u[3 * n + 2] = (float)(pz / rho);
         }
         if (o_phi) {
-            const float a = rr / k.rho_r0, b = rb / k.rho_b0;
-            o_phi[n] = (a - b) / (a + b);
+            const double a = rr / k.rho_r0, b = rb / k.rho_b0;
+            o_phi[n] = (float)((a - b) / (a + b));
         }
         acc[0] = rr;
         acc[1] = rb;

@@ -24,6 +24,11 @@ __host__ __device__ constexpr float wgt(int i)
     return csq(i) == 0 ? 8.0f / 27.0f : csq(i) == 1 ? 2.0f / 27.0f : csq(i) == 2 ? 1.0f / 54.0f : 1.0f / 216.0f;
 }
 
+__host__ __device__ constexpr double wgtd(int i)
+{
+    return csq(i) == 0 ? 8.0 / 27.0 : csq(i) == 1 ? 2.0 / 27.0 : csq(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+}
+
 // 1/|c_i| for i >= 1 (unused for i = 0)
 __host__ __device__ constexpr float inv_len(int i)
 {

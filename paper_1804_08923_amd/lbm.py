@@ -212,9 +212,9 @@ class LBM:
         _check(self.lib, self.lib.lbm_profile(self.h, 1 if enable else 0))
 
     def profile_read(self):
-        """(ms, launches) per kernel: index 0 density pass, 1 fused kernel."""
-        ms = (C.c_double * 2)()
-        n = (C.c_int64 * 2)()
+        """(ms, launches): index 0 density pass, 1 fused kernel, 2 boundary kernels."""
+        ms = (C.c_double * 3)()
+        n = (C.c_int64 * 3)()
         _check(self.lib, self.lib.lbm_profile_read(self.h, ms, n))
         return list(ms), list(n)
 

@@ -39,13 +39,14 @@ def test_query_sizes(lib):
         prob = mk()
         s = lbm.lbm_query_sizes(lbm.make_params(prob))
         N = prob.n_nodes
+        NP = (prob.nx + 2) * (prob.ny + 2) * (prob.nz + 2)
         assert s.n_nodes == N
-        assert s.pop_bytes == 54 * N * 4
+        assert s.pop_bytes == 54 * NP * 4
         assert s.state_bytes == 54 * N * 4
-        assert s.field_bytes == 12 * N
-        assert s.hist_bytes == (54 * prob.nx * prob.ny * 4 if prob.bc == "jet" else 0)
+        assert s.field_bytes == 44 * NP
+        assert s.hist_bytes == (2 * 54 * prob.nx * prob.ny * 4 if prob.bc == "jet" else 0)
         for st, b in (("bf16", 2), ("fp16", 2)):
-            assert lbm.lbm_query_sizes(lbm.make_params(prob.replace(storage=st))).pop_bytes == 54 * N * b
+            assert lbm.lbm_query_sizes(lbm.make_params(prob.replace(storage=st))).pop_bytes == 54 * NP * b
 
 
 @pytest.mark.parametrize("field,value,code", [

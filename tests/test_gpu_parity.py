@@ -74,11 +74,14 @@ def test_single_step_random_state(torch, orc, shape):
 
 
 def _internal_state(sim, prob):
-    """The GPU's stored state right after set_state (unshifted): d_i = f_i - w_i rho_b0
-    and f^r_i in FP32, converted exactly to (fr, fb) in FP64 for the oracle."""
+    """The GPU's stored state right after set_state (general form at each node of the
+    padded lattice): d_i = f_i - w_i rho_b0 and f^r_i in FP32, converted exactly to
+    (fr, fb) in FP64 for the oracle."""
     from harness import Q as _Q
-    N = prob.n_nodes
-    raw = sim.pop_a.view(torch_mod().float32)[: 2 * _Q * N].reshape(2 * _Q, N).cpu().numpy().astype(np.float64)
+    NP = (prob.nx + 2) * (prob.ny + 2) * (prob.nz + 2)
+    raw = sim.pop_a.view(torch_mod().float32)[: 2 * _Q * NP].reshape(2 * _Q, prob.nz + 2, prob.ny + 2, prob.nx + 2)
+    # interior of the padded lattice, node order
+    raw = raw[:, 1:-1, 1:-1, 1:-1].reshape(2 * _Q, -1).cpu().numpy().astype(np.float64)
     from oracle import Oracle
     _, w = Oracle("f64").lattice()
     d, fr = raw[:_Q], raw[_Q:]
