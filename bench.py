@@ -16,7 +16,6 @@ cpu_baseline = the FP64 oracle on the host cores, on a bounded sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -44,17 +43,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("lbm_kernels.h", "lbm_lattice.h"):
-        with open(os.path.join(ROOT, "paper_1804_08923_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(storage):
     """HBM bytes per fused-kernel launch from committed rocprofv3 counter runs,
     used only while the kernel source is unchanged since they were taken."""
+    from paper_1804_08923_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
