@@ -106,6 +106,47 @@ def run_leg(prob, steps, warmup):
                 step_roofline_frac=mlups / (HBM_PEAK_GBS * 1e9 / STEP_BYTES[st] / 1e6))
 
 
+def adjoint_leg(prob, nadj=10):
+    """Cost of one adjoint step (lbm_adjoint_step) at a developed state, and of
+    recomputing one forward state from a checkpoint (set_state + step +
+    get_state), both timed with events on the library's stream."""
+    import torch
+
+    from paper_1804_08923_amd.lbm import LBM
+    sim = LBM(prob, device="cuda:0", adjoint=True)
+    sim.step(50)
+    st = sim.get_state()
+    t = sim.time
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(5)
+    lam = [torch.randn(st.shape, generator=g, device="cuda:0", dtype=torch.float32), torch.empty_like(st)]
+    dA = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    du = torch.zeros(prob.nx * prob.ny, dtype=torch.float32, device="cuda:0")
+    for i in range(2):
+        sim.adjoint_step(st, t, lam[i % 2], lam[1 - i % 2], dA, du)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(nadj):
+        sim.adjoint_step(st, t, lam[i % 2], lam[1 - i % 2], dA, du)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / nadj
+    finite = bool(torch.isfinite(lam[nadj % 2]).all().item()) and bool(torch.isfinite(dA).all().item())
+    e0.record()
+    for _ in range(nadj):
+        sim.set_state(st, t)
+        sim.step(1)
+        sim.get_state()
+    e1.record()
+    torch.cuda.synchronize()
+    rec_ms = e0.elapsed_time(e1) / nadj
+    sim.close()
+    del sim, st, lam
+    torch.cuda.empty_cache()
+    return dict(adjoint_ms=adj_ms, recompute_ms=rec_ms, finite=finite)
+
+
 def cpu_baseline(prob, nz_sample=64, steps=8):
     """The FP64 oracle on a slab of the same jet (full cross-section, nz_sample planes)."""
     from oracle import Oracle
@@ -132,6 +173,7 @@ def main():
     ap.add_argument("--workload", default="jet-128x128x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the BF16/FP16 storage legs")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-step timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (calibrates hardware byte counters)")
     args = ap.parse_args()
@@ -172,6 +214,15 @@ def main():
                         "fused_kernel_ms": round(r["fused_ms"], 4), "fused_kernel_gbs": round(r["fused_gbs"], 1),
                         "finite": r["finite"]}
             log(f"bench: {st} {r['mlups']:.0f} MLUPS ({r['mlups'] / main_leg['mlups']:.2f}x fp32)")
+    adj = None
+    if not args.no_adjoint:
+        a = adjoint_leg(prob)
+        adj = {"adjoint_step_ms": round(a["adjoint_ms"], 4), "forward_step_ms": round(main_leg["ms_per_step"], 4),
+               "ratio": round(a["adjoint_ms"] / main_leg["ms_per_step"], 3),
+               "recompute_step_ms": round(a["recompute_ms"], 4), "finite": a["finite"],
+               "note": "adjoint step alone; recompute = set_state + step + get_state of one checkpointed state"}
+        log(f"bench: adjoint step {a['adjoint_ms']:.3f} ms = {adj['ratio']:.2f}x forward, "
+            f"recompute {a['recompute_ms']:.3f} ms")
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
@@ -206,7 +257,8 @@ def main():
         "boundary_kernels_ms": round(main_leg["boundary_ms"], 4),
         "cpu_baseline": cpu,
         "storage_legs": legs,
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": adj["ratio"] if adj else None,
+        "adjoint": adj,
         "finite": main_leg["finite"],
         "paper_context": PAPER_CONTEXT,
     }

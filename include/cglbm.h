@@ -98,7 +98,7 @@ typedef struct lbm_buffers {
     float* hist;             /* hist_bytes; may be NULL when bc == LBM_BC_PERIODIC */
     double* audit;           /* audit_bytes */
     const float* inlet_uz;   /* NULL: uniform inlet_u; else nx*ny axial velocities (x fastest) */
-    void* adjoint;           /* adjoint_bytes, or NULL if lbm_adjoint_step is never called */
+    void* adjoint;           /* adjoint_bytes, 256-byte aligned, or NULL if lbm_adjoint_step is never called */
 } lbm_buffers;
 
 typedef struct lbm_handle lbm_handle;
@@ -146,15 +146,28 @@ int lbm_set_state(lbm_handle* h, const float* state, int64_t t);
  * the last lbm_set_state). */
 int64_t lbm_time(const lbm_handle* h);
 
-/* One reverse (adjoint) step.  state_t (device, lbm_get_state layout) is the
- * forward state at time t; lambda (device, same layout) holds on entry the
- * adjoint of the state at t+1 and on return the adjoint at t.  dJ_dA (device,
- * 1 double) and dJ_du_in (device, nx*ny floats, may be NULL) are incremented
- * by this step's contribution to the gradients with respect to A and to the
- * inlet axial-velocity profile.  Uses buf->adjoint as work space and leaves
- * the forward state of the handle untouched.  FP32 storage only. */
-int lbm_adjoint_step(lbm_handle* h, const float* state_t, float* lambda, double* dJ_dA,
-                     float* dJ_du_in);
+/* One reverse (adjoint) step of the time step t -> t+1 (not in the paper:
+ * the hand-written reverse mode of every operation listed at the top of
+ * this file, including the jet boundaries).
+ *   state_t    device, lbm_get_state layout: the forward state at time t
+ *              (the caller recomputes it, e.g. from a checkpoint);
+ *   t          its time level (the inlet noise depends on it);
+ *   lambda_in  device, same layout: cotangent of the state at t+1;
+ *   lambda_out device, same layout, written: (d x_{t+1} / d x_t)^T lambda_in;
+ *              must not alias lambda_in or state_t;
+ *   dJ_dA      device, 1 double, incremented by lambda_in . d x_{t+1}/dA;
+ *   dJ_du_in   device, nx*ny floats or NULL; jet only: incremented by
+ *              lambda_in . d x_{t+1}/d u_in, u_in the inlet axial-velocity
+ *              profile (entries outside the inlet circle stay unchanged).
+ * The step is differentiated in exact arithmetic: the rounding of the
+ * population storage format is not modelled, so any storage works.  At the
+ * non-differentiable points (|grad phi| = grad_eps, u_z = 0 in the outflow
+ * condition) the one-sided derivative of the branch taken is used.  Needs
+ * buf->adjoint (adjoint_bytes); overwrites the per-node field scratch that
+ * every lbm_step recomputes, and leaves the populations and the time level
+ * of the handle unchanged.  Enqueued on the handle's stream; no host sync. */
+int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float* lambda_in,
+                     float* lambda_out, double* dJ_dA, float* dJ_du_in);
 
 /* Instrumentation: with enable != 0, lbm_step records HIP events on its
  * stream around its kernel groups (density pass; fused collide-recolour-

@@ -203,7 +203,7 @@ int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
     out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * 2ull * Q * plane * sizeof(float) : 0;
     out->audit_bytes = (nblk + 1) * 5 * sizeof(double);
     out->inlet_bytes = plane * sizeof(float);
-    out->adjoint_bytes = adjoint_work_bytes(N);
+    out->adjoint_bytes = adjoint_layout(NP, plane, nblk, nullptr, nullptr);
     out->state_bytes = 2ull * Q * N * sizeof(float);
     return LBM_OK;
 }
@@ -219,7 +219,8 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
         return fail(LBM_ERR_INVALID_ARG, "population, field and audit buffers are required");
     if (p->bc == LBM_BC_JET && !buf->hist) return fail(LBM_ERR_INVALID_ARG, "the jet needs the outlet history buffer");
     if (!aligned(buf->pop_a, 256) || !aligned(buf->pop_b, 256) || !aligned(buf->fields, 16) ||
-        !aligned(buf->audit, 8) || (buf->hist && !aligned(buf->hist, 16)))
+        !aligned(buf->audit, 8) || (buf->hist && !aligned(buf->hist, 16)) ||
+        (buf->adjoint && !aligned(buf->adjoint, 256)))
         return fail(LBM_ERR_INVALID_ARG, "misaligned buffer");
     if (buf->pop_a == buf->pop_b) return fail(LBM_ERR_INVALID_ARG, "population buffers must differ");
     if (p->init == LBM_INIT_FIELDS && (!rho_r || !rho_b))
@@ -396,11 +397,58 @@ int lbm_set_state(lbm_handle* h, const float* state, int64_t t)
 
 int64_t lbm_time(const lbm_handle* h) { return h ? (int64_t)h->t : -1; }
 
-int lbm_adjoint_step(lbm_handle* h, const float* state_t, float* lambda, double* dJ_dA, float* dJ_du_in)
+int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float* lambda_in, float* lambda_out,
+                     double* dJ_dA, float* dJ_du_in)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
-    return adjoint_step(h->p, h->k, h->stream, h->adjoint, h->nblk, state_t, lambda, dJ_dA, dJ_du_in, g_err,
-                        sizeof(g_err));
+    if (!h->adjoint) return fail(LBM_ERR_STATE, "no adjoint work buffer was given to lbm_init");
+    if (!state_t || !lambda_in || !lambda_out || !dJ_dA)
+        return fail(LBM_ERR_INVALID_ARG, "state_t, lambda_in, lambda_out and dJ_dA are required");
+    if (lambda_out == lambda_in || (const float*)lambda_out == state_t)
+        return fail(LBM_ERR_INVALID_ARG, "lambda_out must not alias lambda_in or state_t");
+    if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
+    AdjWork w;
+    adjoint_layout(h->k.NP, h->k.plane, (uint64_t)h->nblk, (char*)h->adjoint, &w);
+    KP k = h->k;
+    k.t = t;
+    k.unshifted = 1;
+    k.z0 = 0;
+    k.R = nullptr;
+    auto run = [&](auto bc) -> int {
+        constexpr int BC = decltype(bc)::value;
+        hipLaunchKernelGGL(k_adj_density, h->grid_all, dim3(BLOCK), 0, h->stream, state_t, h->PD, h->XR, k);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
+        LAUNCH_CHECK();
+        if (BC == LBM_BC_JET) {
+            KP kt = k;
+            kt.z0 = h->p.nz - 3;
+            hipLaunchKernelGGL(k_adj_top_post, dim3(h->grid_all.x, 3), dim3(BLOCK), 0, h->stream, state_t, h->PD,
+                               h->XR, w.PS, kt);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_adj_outlet, h->grid_plane, dim3(BLOCK), 0, h->stream, state_t, lambda_in, w.PS,
+                               w.ML, w.DL, k);
+            LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_adj_node<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, state_t, lambda_in, w.ML, h->PD,
+                           h->XR, lambda_out, w.AG0, w.AG1, w.AP, k);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_adj_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, k,
+                           h->ncells);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_adj_fields<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, h->PD,
+                           h->XR, w.DL, lambda_out, k);
+        LAUNCH_CHECK();
+        if (BC == LBM_BC_JET && dJ_du_in) {
+            hipLaunchKernelGGL(k_adj_inlet, h->grid_plane, dim3(BLOCK), 0, h->stream, lambda_in, dJ_du_in, k);
+            LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_adj_sumA, dim3(1), dim3(BLOCK), 0, h->stream, w.AP, h->nblk, dJ_dA);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    };
+    if (h->p.bc == LBM_BC_PERIODIC) return run(IntC<LBM_BC_PERIODIC>{});
+    return run(IntC<LBM_BC_JET>{});
 }
 
 int lbm_profile(lbm_handle* h, int enable)

@@ -78,7 +78,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_set_state.argtypes = [vp, vp, i64]
     lib.lbm_time.argtypes = [vp]
     lib.lbm_time.restype = i64
-    lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_adjoint_step.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
     lib.lbm_profile.argtypes = [vp, C.c_int]
     lib.lbm_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.lbm_destroy.argtypes = [vp]
@@ -204,9 +204,16 @@ class LBM:
     def time(self) -> int:
         return int(self.lib.lbm_time(self.h))
 
-    def adjoint_step(self, state_t, lam, dJ_dA, dJ_du_in=None):
-        _check(self.lib, self.lib.lbm_adjoint_step(self.h, state_t.data_ptr(), lam.data_ptr(), dJ_dA.data_ptr(),
-                                                   _ptr(dJ_du_in)))
+    def adjoint_step(self, state_t, t: int, lam_in, lam_out, dJ_dA, dJ_du_in=None):
+        """One reverse step (see lbm_adjoint_step): lam_out = (d x_{t+1}/d x_t)^T lam_in;
+        dJ_dA (float64, 1 element) and dJ_du_in (float32, nx*ny) are incremented."""
+        for a in (state_t, lam_in, lam_out):
+            assert a.dtype == self.torch.float32 and a.is_contiguous() and a.numel() == 2 * Q * self.sizes.n_nodes
+        assert dJ_dA.dtype == self.torch.float64 and dJ_dA.numel() >= 1
+        if dJ_du_in is not None:
+            assert dJ_du_in.dtype == self.torch.float32 and dJ_du_in.numel() == self.prob.nx * self.prob.ny
+        _check(self.lib, self.lib.lbm_adjoint_step(self.h, state_t.data_ptr(), int(t), lam_in.data_ptr(),
+                                                   lam_out.data_ptr(), dJ_dA.data_ptr(), _ptr(dJ_du_in)))
 
     def profile(self, enable: bool = True):
         _check(self.lib, self.lib.lbm_profile(self.h, 1 if enable else 0))
