@@ -203,7 +203,7 @@ int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
     out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * 2ull * Q * plane * sizeof(float) : 0;
     out->audit_bytes = (nblk + 1) * 5 * sizeof(double);
     out->inlet_bytes = plane * sizeof(float);
-    out->adjoint_bytes = adjoint_layout(NP, plane, nblk, nullptr, nullptr);
+    out->adjoint_bytes = adjoint_layout(NP, N, plane, nblk, nullptr, nullptr);
     out->state_bytes = 2ull * Q * N * sizeof(float);
     return LBM_OK;
 }
@@ -408,7 +408,7 @@ int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float
         return fail(LBM_ERR_INVALID_ARG, "lambda_out must not alias lambda_in or state_t");
     if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
     AdjWork w;
-    adjoint_layout(h->k.NP, h->k.plane, (uint64_t)h->nblk, (char*)h->adjoint, &w);
+    adjoint_layout(h->k.NP, h->k.N, h->k.plane, (uint64_t)h->nblk, (char*)h->adjoint, &w);
     KP k = h->k;
     k.t = t;
     k.unshifted = 1;
@@ -416,34 +416,34 @@ int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float
     k.R = nullptr;
     auto run = [&](auto bc) -> int {
         constexpr int BC = decltype(bc)::value;
-        hipLaunchKernelGGL(k_adj_density, h->grid_all, dim3(BLOCK), 0, h->stream, state_t, h->PD, h->XR, k);
+        hipLaunchKernelGGL(k_adj_density, h->grid_all, dim3(BLOCK), 0, h->stream, state_t, h->PD, h->XR, w.MOM, k);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
         LAUNCH_CHECK();
         if (BC == LBM_BC_JET) {
             KP kt = k;
             kt.z0 = h->p.nz - 3;
-            hipLaunchKernelGGL(k_adj_top_post, dim3(h->grid_all.x, 3), dim3(BLOCK), 0, h->stream, state_t, h->PD,
+            hipLaunchKernelGGL(k_adj_top_post, dim3(h->grid_all.x, 3), dim3(BLOCK), 0, h->stream, w.MOM, h->PD,
                                h->XR, w.PS, kt);
             LAUNCH_CHECK();
             hipLaunchKernelGGL(k_adj_outlet, h->grid_plane, dim3(BLOCK), 0, h->stream, state_t, lambda_in, w.PS,
                                w.ML, w.DL, k);
             LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_adj_node<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, state_t, lambda_in, w.ML, h->PD,
-                           h->XR, lambda_out, w.AG0, w.AG1, w.AP, k);
+        hipLaunchKernelGGL(k_adj_node<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, w.MOM, lambda_in, w.ML, h->PD,
+                           h->XR, w.LC, w.AG0, w.AG1, w.AP, k);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_adj_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, k,
                            h->ncells);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_adj_fields<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, h->PD,
-                           h->XR, w.DL, lambda_out, k);
+                           h->XR, w.DL, w.LC, lambda_out, k);
         LAUNCH_CHECK();
         if (BC == LBM_BC_JET && dJ_du_in) {
             hipLaunchKernelGGL(k_adj_inlet, h->grid_plane, dim3(BLOCK), 0, h->stream, lambda_in, dJ_du_in, k);
             LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_adj_sumA, dim3(1), dim3(BLOCK), 0, h->stream, w.AP, h->nblk, dJ_dA);
+        hipLaunchKernelGGL(k_adj_sumA, dim3(1), dim3(SUM_BLOCK), 0, h->stream, w.AP, h->nblk, dJ_dA);
         LAUNCH_CHECK();
         return LBM_OK;
     };

@@ -6,15 +6,17 @@
 // and lambda_{t+1} . d x_{t+1}/d u_in (the inlet axial-velocity profile) to the
 // caller's gradient accumulators.  The forward quantities of step t are
 // recomputed from x_t (no tape).  Passes:
-//   1. densities of x_t -> (phi, rho - rho_b0), rho_r/rho per padded node; ghost shell
+//   1. densities of x_t -> (phi, rho - rho_b0), rho_r/rho per padded node, and the
+//      raw moments of the colour-blind deviations up to second order; ghost shell
 //   2. (jet) outlet: the convective condition of the outlet plane depends on the
 //      streamed populations of the plane below; its adjoint is formed first
 //      from a forward recomputation of the three top planes
 //   3. per node: reverse streaming (gather of lambda_{t+1} from x + c_i, with the
 //      reflections, inlet absorption and outlet rules of the forward step),
 //      then the node vector-Jacobian product (lbm_adjoint_node.h); writes the
-//      cotangent of the 27 colour-blind deviations and 8 stencil/centre
-//      cotangents, and a block partial of dJ/dA
+//      cotangents of the 10 raw moments (the cotangent of deviation i is their
+//      quadratic polynomial in c_i), 8 stencil/centre cotangents and a block
+//      partial of dJ/dA
 //   4. ghost shell of the stencil cotangents (periodic copies; jet: zero,
 //      plus the sums that the mirrored ghost fields route back to the wall nodes)
 //   5. per node: transpose of the gradient stencil, chain rule through
@@ -27,6 +29,8 @@ namespace cglbm {
 
 // ---------------------------------------------------------------- work buffer
 struct AdjWork {
+    float* MOM;     // raw moments m0, j (3), P (xx yy zz xy xz yz) of the deviations [10][N]
+    float* LC;      // their cotangents [10][N]
     float4* AG0;    // (L grad phi, L phi_centre) per padded node
     float4* AG1;    // (L grad rho, L rho_r/rho) per padded node
     float2* GH;     // jet: stencil cotangents gathered at ghost cells (phi, rho)
@@ -38,7 +42,7 @@ struct AdjWork {
 
 inline uint64_t align256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
 
-inline uint64_t adjoint_layout(uint64_t NP, uint64_t plane, uint64_t nblk, char* base, AdjWork* w)
+inline uint64_t adjoint_layout(uint64_t NP, uint64_t N, uint64_t plane, uint64_t nblk, char* base, AdjWork* w)
 {
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
@@ -46,6 +50,8 @@ inline uint64_t adjoint_layout(uint64_t NP, uint64_t plane, uint64_t nblk, char*
         off += align256(bytes);
         return p;
     };
+    char* mom = take(N * 10 * 4);
+    char* lc = take(N * 10 * 4);
     char* a0 = take(NP * 16);
     char* a1 = take(NP * 16);
     char* gh = take(NP * 8);
@@ -54,6 +60,8 @@ inline uint64_t adjoint_layout(uint64_t NP, uint64_t plane, uint64_t nblk, char*
     char* dl = take(2ull * Q * plane * 4);
     char* ap = take((nblk + 1) * 8);
     if (w) {
+        w->MOM = (float*)mom;
+        w->LC = (float*)lc;
         w->AG0 = (float4*)a0;
         w->AG1 = (float4*)a1;
         w->GH = (float2*)gh;
@@ -71,65 +79,65 @@ __device__ __forceinline__ uint32_t nidx(const KP& k, int x, int y, int z)
     return ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
 }
 
-// colour-blind deviations d_i of a node of an FP32 state (fr planes, then fb)
-__device__ __forceinline__ void state_dev(const KP& k, const float* __restrict__ st, uint32_t n, float* d)
-{
-    const size_t N = k.N;
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-        d[i] = (float)(((double)st[(size_t)i * N + n] + (double)st[(size_t)(Q + i) * N + n]) -
-                       wgtd(i) * (double)k.rho_b0);
-}
-
-// 1. densities of an FP32 state
+// 1. densities and raw moments of the deviations d_i = f^r_i + f^b_i - w_i rho_b0
+// of an FP32 state (fr planes, then fb), accumulated in FP64
 __global__ __launch_bounds__(BLOCK) void k_adj_density(const float* __restrict__ st, float2* __restrict__ PD,
-                                                        float* __restrict__ XR, KP k)
+                                                        float* __restrict__ XR, float* __restrict__ MOM, KP k)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
     const size_t N = k.N;
     const uint32_t n = nidx(k, nd.x, nd.y, nd.z);
-    double rr = 0.0, rb = 0.0;
+    double rr = 0.0;
+    MomT<double> M;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        rr += (double)st[(size_t)i * N + n];
-        rb += (double)st[(size_t)(Q + i) * N + n];
+        const double a = st[(size_t)i * N + n], b = st[(size_t)(Q + i) * N + n];
+        rr += a;
+        M.add(i, (a + b) - wgtd(i) * (double)k.rho_b0);
     }
-    store_fields_sums(PD, XR, k, nd.n, rr + rb - (double)k.rho_b0, rr);
+    store_fields_sums(PD, XR, k, nd.n, M.m0, rr);
+    const double mv[10] = {M.m0, M.j[0], M.j[1], M.j[2], M.P[0], M.P[1], M.P[2], M.P[3], M.P[4], M.P[5]};
+#pragma unroll
+    for (int a = 0; a < 10; ++a) MOM[(size_t)a * N + n] = (float)mv[a];
 }
 
-// forward node quantities of node nd from the state and the field stencil
-__device__ __forceinline__ void adj_node_inputs(const KP& k, const float* __restrict__ st,
-                                                const float2* __restrict__ PD, const float* __restrict__ XR,
-                                                const Node& nd, float* d, float& phic, float& xr, double (&g)[6])
+// forward node quantities of node nd from its moments and the field stencil
+__device__ __forceinline__ void adj_node_fwd(const KP& k, const float* __restrict__ MOM,
+                                             const float2* __restrict__ PD, const float* __restrict__ XR,
+                                             const Node& nd, NodeFwdT<float>& f, float& xr)
 {
-    state_dev(k, st, nidx(k, nd.x, nd.y, nd.z), d);
-    phic = ldp(PD, nd.n).x;
+    const size_t N = k.N;
+    const uint32_t n = nidx(k, nd.x, nd.y, nd.z);
+    MomT<float> M;
+    M.m0 = MOM[n];
+    for (int a = 0; a < 3; ++a) M.j[a] = MOM[(size_t)(1 + a) * N + n];
+    for (int a = 0; a < 6; ++a) M.P[a] = MOM[(size_t)(4 + a) * N + n];
+    const float phic = ldp(PD, nd.n).x;
     xr = ldp(XR, nd.n);
-    for (int a = 0; a < 6; ++a) g[a] = 0.0;
+    double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     gradients(PD, k, nd.n, g);
+    node_fwd<float>(k, M, phic, g, f);
 }
 
 // 2a. (jet) post-collision populations of planes nz - 3 .. nz - 1 (z0 = nz - 3)
-__global__ __launch_bounds__(BLOCK) void k_adj_top_post(const float* __restrict__ st, const float2* __restrict__ PD,
+__global__ __launch_bounds__(BLOCK) void k_adj_top_post(const float* __restrict__ MOM, const float2* __restrict__ PD,
                                                          const float* __restrict__ XR, float* __restrict__ PS, KP k)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
-    float d[Q], phic, xr;
-    double g[6];
-    adj_node_inputs(k, st, PD, XR, nd, d, phic, xr, g);
-    NodeFwd f;
-    node_fwd(k, d, phic, g, f);
-    double fp[Q], V[3];
-    node_post(k, f, xr, fp, V);
+    NodeFwdT<float> f;
+    float xr;
+    adj_node_fwd(k, MOM, PD, XR, nd, f, xr);
+    float fp[Q], V[3];
+    node_post<float>(k, f, xr, fp, V);
     const int zz = nd.z - k.z0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        double fr, fb;
-        recolour_dir(i, xr, fp[i], V, fr, fb);
-        PS[((size_t)i * 3 + zz) * k.plane + nd.q] = (float)fr;
-        PS[((size_t)(Q + i) * 3 + zz) * k.plane + nd.q] = (float)fb;
+        float fr, fb;
+        recolour_dir<float>(i, xr, fp[i], V, fr, fb);
+        PS[((size_t)i * 3 + zz) * k.plane + nd.q] = fr;
+        PS[((size_t)(Q + i) * 3 + zz) * k.plane + nd.q] = fb;
     }
 }
 
@@ -185,38 +193,50 @@ __global__ __launch_bounds__(BLOCK) void k_adj_outlet(const float* __restrict__ 
 }
 
 // 3. reverse streaming and node VJP
-template <int BC>
+// direction I with the components in mask m reversed, by selects (m varies per lane)
+template <int I>
+__device__ __forceinline__ int mirror_sel(int m)
+{
+    constexpr int t0 = mirror_dir(I, 0), t1 = mirror_dir(I, 1), t2 = mirror_dir(I, 2), t3 = mirror_dir(I, 3);
+    constexpr int t4 = mirror_dir(I, 4), t5 = mirror_dir(I, 5), t6 = mirror_dir(I, 6), t7 = mirror_dir(I, 7);
+    return (m & 4) ? ((m & 2) ? ((m & 1) ? t7 : t6) : ((m & 1) ? t5 : t4))
+                   : ((m & 2) ? ((m & 1) ? t3 : t2) : ((m & 1) ? t1 : t0));
+}
+
+// cotangents of the post-collision populations of this node: those of the
+// populations they become after streaming (x + c_i, reversed on every axis
+// that leaves the lattice), zero where the forward step overwrites them
+template <int BC, int I = 0>
 __device__ __forceinline__ void adj_gather(const KP& k, const float* __restrict__ lam, const float* __restrict__ ML,
                                            const Node& nd, float* Lr, float* Lb)
 {
-    const size_t N = k.N;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        int dx = nd.x + kCX[i], dy = nd.y + kCY[i], dz = nd.z + kCZ[i];
+    if constexpr (I < Q) {
+        const size_t N = k.N;
+        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
+        int dx = nd.x + cx, dy = nd.y + cy, dz = nd.z + cz;
         float vr = 0.f, vb = 0.f;
         if (BC == LBM_BC_PERIODIC) {
-            dx = wrapc(dx, k.nx);
-            dy = wrapc(dy, k.ny);
-            dz = wrapc(dz, k.nz);
+            if (cx) dx = wrapc(dx, k.nx);
+            if (cy) dy = wrapc(dy, k.ny);
+            if (cz) dz = wrapc(dz, k.nz);
             const size_t n = nidx(k, dx, dy, dz);
-            vr = lam[(size_t)i * N + n];
-            vb = lam[(size_t)(Q + i) * N + n];
+            vr = lam[(size_t)I * N + n];
+            vb = lam[(size_t)(Q + I) * N + n];
         } else {
-            // destination of post-collision population i of this node: x + c_i with
-            // the components reversed on every axis that leaves the lattice
             int m = 0;
             bool lost = false;
-            if (dx < 0 || dx >= k.nx) { m |= 1; dx = nd.x; }
-            if (dy < 0 || dy >= k.ny) { m |= 2; dy = nd.y; }
-            if (dz < 0) {
+            if (cx && (dx < 0 || dx >= k.nx)) { m |= 1; dx = nd.x; }
+            if (cy && (dy < 0 || dy >= k.ny)) { m |= 2; dy = nd.y; }
+            if (cz < 0 && dz < 0) {
                 // the ghost below this node is an inlet cell: overwritten by the inflow
                 if (m == 0 && inlet_inside(k, nd.x, nd.y)) lost = true;
                 m |= 4;
                 dz = nd.z;
             }
-            if (dz >= k.nz - 1) lost = true;  // outlet plane: replaced by the convective condition
+            if (cz > 0 && dz >= k.nz - 1) lost = true;   // replaced by the convective condition
+            if (cz == 0 && dz == k.nz - 1) lost = true;
             if (!lost) {
-                const int j = kMirror.v[i * 8 + m];
+                const int j = cx || cy || cz < 0 ? mirror_sel<I>(m) : I;
                 if (dz == k.nz - 2) {
                     const size_t q = (size_t)dy * k.nx + dx;
                     vr = ML[(size_t)j * k.plane + q];
@@ -228,39 +248,36 @@ __device__ __forceinline__ void adj_gather(const KP& k, const float* __restrict_
                 }
             }
         }
-        Lr[i] = vr;
-        Lb[i] = vb;
+        Lr[I] = vr;
+        Lb[I] = vb;
+        adj_gather<BC, I + 1>(k, lam, ML, nd, Lr, Lb);
     }
 }
 
 template <int BC>
-__global__ __launch_bounds__(BLOCK) void k_adj_node(const float* __restrict__ st, const float* __restrict__ lam_in,
-                                                     const float* __restrict__ ML, const float2* __restrict__ PD,
-                                                     const float* __restrict__ XR, float* __restrict__ lam_out,
-                                                     float4* __restrict__ AG0, float4* __restrict__ AG1,
-                                                     double* __restrict__ AP, KP k)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adj_node(
+    const float* __restrict__ MOM, const float* __restrict__ lam_in, const float* __restrict__ ML,
+    const float2* __restrict__ PD, const float* __restrict__ XR, float* __restrict__ LC, float4* __restrict__ AG0,
+    float4* __restrict__ AG1, double* __restrict__ AP, KP k)
 {
     const Node nd = this_node(k);
     double acc[1] = {0.0};
     if (nd.valid) {
-        float d[Q], phic, xr;
-        double g[6];
-        adj_node_inputs(k, st, PD, XR, nd, d, phic, xr, g);
-        NodeFwd f;
-        node_fwd(k, d, phic, g, f);
-        double fp[Q], V[3];
-        node_post(k, f, xr, fp, V);
+        NodeFwdT<float> f;
+        float xr;
+        adj_node_fwd(k, MOM, PD, XR, nd, f, xr);
         float Lr[Q], Lb[Q];
         adj_gather<BC>(k, lam_in, ML, nd, Lr, Lb);
-        NodeAdj o;
-        node_vjp(k, f, xr, fp, Lr, Lb, o);
+        NodeAdjT<float> o;
+        node_vjp<float>(k, f, xr, Lr, Lb, o);
         const size_t N = k.N;
         const uint32_t n = nidx(k, nd.x, nd.y, nd.z);
+        const float lc[10] = {o.Lm0, o.Lj[0], o.Lj[1], o.Lj[2], o.Lq[0], o.Lq[1], o.Lq[2], o.Lq[3], o.Lq[4], o.Lq[5]};
 #pragma unroll
-        for (int i = 0; i < Q; ++i) lam_out[(size_t)i * N + n] = (float)o.Ld[i];
-        stp(AG0, nd.n, make_float4((float)o.Lgp[0], (float)o.Lgp[1], (float)o.Lgp[2], (float)o.Lphic));
-        stp(AG1, nd.n, make_float4((float)o.Lgr[0], (float)o.Lgr[1], (float)o.Lgr[2], (float)o.Lxr));
-        acc[0] = o.LA;
+        for (int a = 0; a < 10; ++a) LC[(size_t)a * N + n] = lc[a];
+        stp(AG0, nd.n, make_float4(o.Lgp[0], o.Lgp[1], o.Lgp[2], o.Lphic));
+        stp(AG1, nd.n, make_float4(o.Lgr[0], o.Lgr[1], o.Lgr[2], o.Lxr));
+        acc[0] = (double)o.LA;
     }
     block_partials<1>(acc, AP, blockIdx.y * gridDim.x + blockIdx.x);
 }
@@ -309,19 +326,19 @@ template <int BC>
 __global__ __launch_bounds__(BLOCK) void k_adj_fields(const float4* __restrict__ AG0, const float4* __restrict__ AG1,
                                                        const float2* __restrict__ GH, const float2* __restrict__ PD,
                                                        const float* __restrict__ XR, const float* __restrict__ DL,
-                                                       float* __restrict__ lam_out, KP k)
+                                                       const float* __restrict__ LC, float* __restrict__ lam_out, KP k)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
-    double Lphi = ldp(AG0, nd.n).w, Lrf = 0.0;
-    const double Lxr = ldp(AG1, nd.n).w;
+    float Lphi = ldp(AG0, nd.n).w, Lrf = 0.f;
+    const float Lxr = ldp(AG1, nd.n).w;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const uint32_t s = nd.n - (uint32_t)doff(k, kCX[i], kCY[i], kCZ[i]);
         const float4 a0 = ldp(AG0, s), a1 = ldp(AG1, s);
-        const double w3 = 3.0 * wgtd(i);
-        Lphi += w3 * (kCX[i] * (double)a0.x + kCY[i] * (double)a0.y + kCZ[i] * (double)a0.z);
-        Lrf += w3 * (kCX[i] * (double)a1.x + kCY[i] * (double)a1.y + kCZ[i] * (double)a1.z);
+        const float w3 = 3.f * wgt(i);
+        Lphi += w3 * (kCX[i] * a0.x + kCY[i] * a0.y + kCZ[i] * a0.z);
+        Lrf += w3 * (kCX[i] * a1.x + kCY[i] * a1.y + kCZ[i] * a1.z);
     }
     if (BC == LBM_BC_JET) {
         // ghost cells whose mirrored field value is this node's
@@ -345,21 +362,31 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fields(const float4* __restrict__
     const double rr = (double)ldp(XR, nd.n) * rho, rb = rho - rr;
     const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
     const double ab2 = (a + b) * (a + b);
-    const double Lrr = Lphi * 2.0 * b / (ab2 * (double)k.rho_r0) + Lrf + Lxr * rb / (rho * rho);
-    const double Lrb = -Lphi * 2.0 * a / (ab2 * (double)k.rho_b0) + Lrf - Lxr * rr / (rho * rho);
+    const float Lrr = (float)(Lphi * 2.0 * b / (ab2 * (double)k.rho_r0) + Lrf + Lxr * rb / (rho * rho));
+    const float Lrb = (float)(-Lphi * 2.0 * a / (ab2 * (double)k.rho_b0) + Lrf - Lxr * rr / (rho * rho));
     const size_t N = k.N;
     const uint32_t n = nidx(k, nd.x, nd.y, nd.z);
+    float lc[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) lc[c] = LC[(size_t)c * N + n];
     const bool top = BC == LBM_BC_JET && nd.z == k.nz - 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double Ld = lam_out[(size_t)i * N + n];
-        double r = Ld + Lrr, bl = Ld + Lrb;
+        const int cx = kCX[i], cy = kCY[i], cz = kCZ[i];
+        float Ld = lc[0];
+        if (cx) Ld += cx * lc[1] + lc[4];
+        if (cy) Ld += cy * lc[2] + lc[5];
+        if (cz) Ld += cz * lc[3] + lc[6];
+        if (cx * cy) Ld += (cx * cy) * lc[7];
+        if (cx * cz) Ld += (cx * cz) * lc[8];
+        if (cy * cz) Ld += (cy * cz) * lc[9];
+        float r = Ld + Lrr, bl = Ld + Lrb;
         if (top) {
             r += DL[(size_t)i * k.plane + nd.q];
             bl += DL[(size_t)(Q + i) * k.plane + nd.q];
         }
-        lam_out[(size_t)i * N + n] = (float)r;
-        lam_out[(size_t)(Q + i) * N + n] = (float)bl;
+        lam_out[(size_t)i * N + n] = r;
+        lam_out[(size_t)(Q + i) * N + n] = bl;
     }
 }
 
@@ -407,16 +434,29 @@ __global__ __launch_bounds__(BLOCK) void k_adj_inlet(const float* __restrict__ l
     dJ_du[q] += (float)acc;
 }
 
-// 6b. dJ/dA += sum of the block partials
-__global__ __launch_bounds__(BLOCK) void k_adj_sumA(const double* __restrict__ AP, int nblk, double* __restrict__ out)
+// 6b. dJ/dA += sum of the block partials (one block of 1024 threads)
+constexpr int SUM_BLOCK = 1024;
+__global__ __launch_bounds__(SUM_BLOCK) void k_adj_sumA(const double* __restrict__ AP, int nblk,
+                                                         double* __restrict__ out)
 {
-    double acc[1] = {0.0};
-    for (int b = threadIdx.x; b < nblk; b += BLOCK) acc[0] += AP[b];
-    __shared__ double red[4];
-    const double s = wave_sum(acc[0]);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * SUM_BLOCK < nblk; b += 4 * SUM_BLOCK) {
+        a0 += AP[b];
+        a1 += AP[b + SUM_BLOCK];
+        a2 += AP[b + 2 * SUM_BLOCK];
+        a3 += AP[b + 3 * SUM_BLOCK];
+    }
+    for (; b < nblk; b += SUM_BLOCK) a0 += AP[b];
+    __shared__ double red[SUM_BLOCK / 64];
+    const double s = wave_sum((a0 + a1) + (a2 + a3));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) out[0] += red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < SUM_BLOCK / 64; ++w) t += red[w];
+        out[0] += t;
+    }
 }
 
 }  // namespace cglbm

@@ -58,17 +58,12 @@ struct StF32 {
     static __device__ __forceinline__ float dec(T v) { return v; }
     static __device__ __forceinline__ T enc(float v) { return v; }
 };
-// bfloat16: upper half of the FP32 pattern, encoded round-to-nearest-even
+// bfloat16: upper half of the FP32 pattern; encoded round-to-nearest-even by
+// the gfx950 conversion instruction (v_cvt_pk_bf16_f32)
 struct StBF16 {
     typedef uint16_t T;
     static __device__ __forceinline__ float dec(T v) { return __uint_as_float((uint32_t)v << 16); }
-    static __device__ __forceinline__ T enc(float v)
-    {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (T)(u >> 16);
-    }
+    static __device__ __forceinline__ T enc(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 };
 // IEEE binary16, hardware conversion (round to nearest even)
 struct StF16 {
@@ -337,27 +332,34 @@ __host__ __device__ constexpr double inv_lend(int i)
     return csq(i) == 1 ? 1.0 : csq(i) == 2 ? 0.70710678118654752440 : 0.57735026918962576451;
 }
 
-// mass and red mass of the pre-collision state at n, accumulated in FP64 (the
-// red populations of a shifted state rebuilt in FP64 with exact weights)
+// Mass and red mass of the pre-collision state at n.  The mass sum m0 runs in
+// FP64 (an exact sum of the stored deviations: mass is conserved up to the
+// storage rounding).  The red mass of a shifted state is written as
+//   rho_r = xr(x) rho + sum_{i>=1} [(xr(x - c_i) - xr(x)) f_i + (w_i/|c_i|) c_i . V(x - c_i)],
+// an FP64 main term plus FP32 corrections that vanish wherever xr and V are
+// uniform (so pure phases carry no rounding bias).
 template <class S, bool SHIFTED, int I = 0>
 __device__ __forceinline__ void accum_density(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
-                                              double& m0, double& rr)
+                                              double& m0, double& rr, float& xr0, float& corr)
 {
     if constexpr (I < Q) {
         constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
         if constexpr (SHIFTED) {
             const uint32_t s = n - (uint32_t)doff(k, cx, cy, cz);
-            const double d = S::dec(ldp(src + (size_t)I * k.NP, s));
+            const float d = S::dec(ldp(src + (size_t)I * k.NP, s));
             const float4 r = ldp(k.R, s);
-            double v = (double)r.x * (d + wgtd(I) * (double)k.rho_b0);
-            if (I != 0) v += (wgtd(I) * inv_lend(I)) * ((double)(cx * r.y) + (double)(cy * r.z) + (double)(cz * r.w));
-            m0 += d;
-            rr += v;
+            m0 += (double)d;
+            if (I == 0) {
+                xr0 = r.x;
+            } else {
+                corr += (r.x - xr0) * (d + wgt(I) * k.rho_b0) +
+                        (wgt(I) * inv_len(I)) * (cx * r.y + cy * r.z + cz * r.w);
+            }
         } else {
             m0 += (double)S::dec(ldp(src + (size_t)I * k.NP, n));
             rr += (double)S::dec(ldp(src + (size_t)(Q + I) * k.NP, n));
         }
-        accum_density<S, SHIFTED, I + 1>(src, k, n, m0, rr);
+        accum_density<S, SHIFTED, I + 1>(src, k, n, m0, rr, xr0, corr);
     }
 }
 
@@ -378,10 +380,13 @@ __global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restri
     const Node nd = this_node(k);
     if (!nd.valid) return;
     double m0 = 0.0, rr = 0.0;
-    if (k.unshifted)
-        accum_density<S, false>(src, k, nd.n, m0, rr);
-    else
-        accum_density<S, true>(src, k, nd.n, m0, rr);
+    float xr0 = 0.f, corr = 0.f;
+    if (k.unshifted) {
+        accum_density<S, false>(src, k, nd.n, m0, rr, xr0, corr);
+    } else {
+        accum_density<S, true>(src, k, nd.n, m0, rr, xr0, corr);
+        rr = (double)xr0 * ((double)k.rho_b0 + m0) + (double)corr;
+    }
     store_fields_sums(PD, XR, k, nd.n, m0, rr);
 }
 
@@ -546,6 +551,26 @@ __device__ __forceinline__ void gradients(const float2* __restrict__ pd, const K
     }
 }
 
+// the same gradients in FP32: each pair difference chi(x + c_i) - chi(x - c_i)
+// is exact for nearly equal values, the weighted sum of 13 of them is well
+// conditioned.  g = (dphi[3], drho[3])
+template <int I = 1>
+__device__ __forceinline__ void gradients_f(const float2* __restrict__ pd, const KP& k, uint32_t n, float (&g)[6])
+{
+    if constexpr (I < Q) {
+        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
+        const int o = doff(k, cx, cy, cz);
+        const float2 a = ldp(pd, n + (uint32_t)o);
+        const float2 b = ldp(pd, n - (uint32_t)o);
+        const float dp = a.x - b.x, dr = a.y - b.y;
+        constexpr float w3 = 3.0f * wgt(I);
+        if (cx) { g[0] += (w3 * cx) * dp; g[3] += (w3 * cx) * dr; }
+        if (cy) { g[1] += (w3 * cy) * dp; g[4] += (w3 * cy) * dr; }
+        if (cz) { g[2] += (w3 * cz) * dp; g[5] += (w3 * cz) * dr; }
+        gradients_f<I + 2>(pd, k, n, g);
+    }
+}
+
 // ---------------------------------------------------------------- ghost writes of the fused kernel
 // A post-collision population J of a boundary node W that would stream out of
 // the lattice is what some interior node pulls from a ghost cell.  Periodic:
@@ -631,75 +656,72 @@ __device__ __forceinline__ constexpr float h2(int c) { return c == 0 ? -1.f : 0.
 // Collision, perturbation and recolouring of one node from its pre-collision
 // colour-blind deviations d, the centre values phic and xr = rho_r/rho and
 // the gradients; writes the 27 post-collision colour-blind deviations to dst
-// and (rho_r/rho, V) of the recolouring to Rout at node n.  The scalar part
-// runs in FP64 (cancellation-prone sums and differences), the per-direction
-// part in FP32.
+// and (rho_r/rho, V) of the recolouring to Rout at node n.  FP64 only where a
+// sum must be exact or an O(1) cancellation happens: the mass m0 and the
+// equilibrium offsets E0, E1 (zero in the pure phases).  The momentum and the
+// second moments are FP32 sums over opposite pairs (pair differences are exact
+// for nearly equal populations, so the momentum of a fluid at rest is exactly
+// zero).
 template <int BC, class S>
 __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const float* d, float phic, float xr,
-                                              const double (&g)[6], typename S::T* __restrict__ dst,
+                                              const float (&g)[6], typename S::T* __restrict__ dst,
                                               float4* __restrict__ Rout)
 {
     const size_t N = k.NP;
     const uint32_t n = nd.n;
     // raw moments of d up to second order
-    double m0 = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-    double pxx = 0.0, pyy = 0.0, pzz = 0.0, pxy = 0.0, pxz = 0.0, pyz = 0.0;
+    double m0d = (double)d[0];
+    float jx = 0.f, jy = 0.f, jz = 0.f;
+    float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double v = d[i];
-        m0 += v;
-        if (kCX[i]) { jx += kCX[i] * v; pxx += v; }
-        if (kCY[i]) { jy += kCY[i] * v; pyy += v; }
-        if (kCZ[i]) { jz += kCZ[i] * v; pzz += v; }
-        if (kCX[i] * kCY[i]) pxy += (kCX[i] * kCY[i]) * v;
-        if (kCX[i] * kCZ[i]) pxz += (kCX[i] * kCZ[i]) * v;
-        if (kCY[i] * kCZ[i]) pyz += (kCY[i] * kCZ[i]) * v;
+    for (int i = 1; i < Q; i += 2) {
+        m0d += (double)d[i] + (double)d[i + 1];
+        const float sp = d[i] + d[i + 1], df = d[i] - d[i + 1];
+        if (kCX[i]) { jx += kCX[i] * df; pxx += sp; }
+        if (kCY[i]) { jy += kCY[i] * df; pyy += sp; }
+        if (kCZ[i]) { jz += kCZ[i] * df; pzz += sp; }
+        if (kCX[i] * kCY[i]) pxy += (kCX[i] * kCY[i]) * sp;
+        if (kCX[i] * kCZ[i]) pxz += (kCX[i] * kCZ[i]) * sp;
+        if (kCY[i] * kCZ[i]) pyz += (kCY[i] * kCZ[i]) * sp;
     }
-    const double rho = (double)k.rho_b0 + m0;
-    const double inv_rho = 1.0 / rho;
+    const float m0 = (float)m0d;
+    const float rhof = (float)((double)k.rho_b0 + m0d);
+    const float inv_rho = 1.f / rhof;
     // interpolated properties (Sec. II): alpha_bar, harmonic nu_bar, s2nu
     const float hpf = 0.5f * (1.f + phic), hmf = 0.5f * (1.f - phic);
     const float nubf = 1.f / (hpf * k.inv_nu_r + hmf * k.inv_nu_b);
     const float s2 = 1.f / (3.f * nubf + 0.5f);
     const double hp = 0.5 * (1.0 + (double)phic);
     const double abar = (double)k.alpha_b + hp * (double)k.dalpha;
-    const double nub = nubf;
-    // body force (Eq. bodyForceJet) and velocity with the half-force term (Eq. Momentum)
-    const double Fx = m0 * k.gx, Fy = m0 * k.gy, Fz = m0 * k.gz;
-    const double ux = (jx + 0.5 * Fx) * inv_rho, uy = (jy + 0.5 * Fy) * inv_rho, uz = (jz + 0.5 * Fz) * inv_rho;
-    // first moments of g = f - f^(e) + F'/2 (vanish up to rounding)
-    const double Gx = jx + 0.5 * Fx - rho * ux, Gy = jy + 0.5 * Fy - rho * uy, Gz = jz + 0.5 * Fz - rho * uz;
-    const double grx = g[3], gry = g[4], grz = g[5];
-    // second raw moments of g without their isotropic parts:
-    // sum f^(e) c_a c_b = iso + rho u_a u_b + nu_bar (u_a dr_b + dr_a u_b); sum F' c_a c_b = u_a F_b + u_b F_a
-    const double qxy = pxy - rho * ux * uy - nub * (ux * gry + grx * uy) + 0.5 * (ux * Fy + uy * Fx);
-    const double qxz = pxz - rho * ux * uz - nub * (ux * grz + grx * uz) + 0.5 * (ux * Fz + uz * Fx);
-    const double qyz = pyz - rho * uy * uz - nub * (uy * grz + gry * uz) + 0.5 * (uy * Fz + uz * Fy);
-    const double qxx = pxx - rho * ux * ux - 2.0 * nub * ux * grx + ux * Fx;
-    const double qyy = pyy - rho * uy * uy - 2.0 * nub * uy * gry + uy * Fy;
-    const double qzz = pzz - rho * uz * uz - 2.0 * nub * uz * grz + uz * Fz;
-    // central moments (shift by u; the zeroth moment of g is exactly 0 here)
-    const double cxy = qxy - ux * Gy - uy * Gx, cxz = qxz - ux * Gz - uz * Gx, cyz = qyz - uy * Gz - uz * Gy;
-    const double cxx = qxx - 2.0 * ux * Gx, cyy = qyy - 2.0 * uy * Gy, czz = qzz - 2.0 * uz * Gz;
-    const double tr3 = (cxx + cyy + czz) * (1.0 / 3.0);
-    const double om = 1.0 - (double)s2;
-    // relaxed deviatoric central moments, scaled by (1 - s2nu)
-    const float kxy = (float)(om * cxy), kxz = (float)(om * cxz), kyz = (float)(om * cyz);
-    const float kxx = (float)(om * (cxx - tr3)), kyy = (float)(om * (cyy - tr3)), kzz = (float)(om * (czz - tr3));
-    // equilibrium offsets in deviation form: E0 = rho abar - w_0 rho_b0, E1 = rho kappa - rho_b0
     const double kap = (27.0 / 19.0) * (1.0 - abar);
-    const double E0 = (double)k.rho_b0 * (hp * (double)k.dalpha + (double)k.a_minus_w0) + m0 * abar;
-    const double E1 = (double)k.rho_b0 * (-(27.0 / 19.0) * hp * (double)k.dalpha + (double)k.kappa_b_m1) + m0 * kap;
-    const double u2d = ux * ux + uy * uy + uz * uz;
-    const double udr = ux * grx + uy * gry + uz * grz;
-    const double uFd = ux * Fx + uy * Fy + uz * Fz;
+    // equilibrium offsets in deviation form: E0 = rho abar - w_0 rho_b0, E1 = rho kappa - rho_b0
+    const double E0 = (double)k.rho_b0 * (hp * (double)k.dalpha + (double)k.a_minus_w0) + m0d * abar;
+    const double E1 = (double)k.rho_b0 * (-(27.0 / 19.0) * hp * (double)k.dalpha + (double)k.kappa_b_m1) + m0d * kap;
+    // body force (Eq. bodyForceJet) and velocity with the half-force term (Eq. Momentum)
+    const float Fxf = m0 * k.gx, Fyf = m0 * k.gy, Fzf = m0 * k.gz;
+    const float uxf = (jx + 0.5f * Fxf) * inv_rho, uyf = (jy + 0.5f * Fyf) * inv_rho, uzf = (jz + 0.5f * Fzf) * inv_rho;
+    const float grxf = g[3], gryf = g[4], grzf = g[5];
+    // second moments of f - f^(e) + F'/2 (its zeroth and first moments vanish, so
+    // these are its central moments): sum f^(e) c_a c_b = iso + rho u_a u_b +
+    // nu_bar (u_a dr_b + dr_a u_b); sum F' c_a c_b = u_a F_b + u_b F_a
+    const float cxy = pxy - rhof * uxf * uyf - nubf * (uxf * gryf + grxf * uyf) + 0.5f * (uxf * Fyf + uyf * Fxf);
+    const float cxz = pxz - rhof * uxf * uzf - nubf * (uxf * grzf + grxf * uzf) + 0.5f * (uxf * Fzf + uzf * Fxf);
+    const float cyz = pyz - rhof * uyf * uzf - nubf * (uyf * grzf + gryf * uzf) + 0.5f * (uyf * Fzf + uzf * Fyf);
+    const float cxx = pxx - rhof * uxf * uxf - 2.f * nubf * uxf * grxf + uxf * Fxf;
+    const float cyy = pyy - rhof * uyf * uyf - 2.f * nubf * uyf * gryf + uyf * Fyf;
+    const float czz = pzz - rhof * uzf * uzf - 2.f * nubf * uzf * grzf + uzf * Fzf;
+    const float tr3 = (cxx + cyy + czz) * (1.f / 3.f);
+    const float om = 1.f - s2;
+    // relaxed deviatoric central moments, scaled by (1 - s2nu)
+    const float kxy = om * cxy, kxz = om * cxz, kyz = om * cyz;
+    const float kxx = om * (cxx - tr3), kyy = om * (cyy - tr3), kzz = om * (czz - tr3);
+    const float u2 = uxf * uxf + uyf * uyf + uzf * uzf;
+    const float udr = uxf * grxf + uyf * gryf + uzf * grzf;
+    const float uF = uxf * Fxf + uyf * Fyf + uzf * Fzf;
 
     // FP32 per-direction part
-    const float uxf = (float)ux, uyf = (float)uy, uzf = (float)uz, u2 = (float)u2d;
-    const float rhof = (float)rho, E1f = (float)E1, uF = (float)uFd;
-    const float Fxf = (float)Fx, Fyf = (float)Fy, Fzf = (float)Fz;
-    const float grxf = (float)grx, gryf = (float)gry, grzf = (float)grz;
-    const float gpx = (float)g[0], gpy = (float)g[1], gpz = (float)g[2];
+    const float E1f = (float)E1;
+    const float gpx = g[0], gpy = g[1], gpz = g[2];
     // back-projection of the relaxed moments: Delta(c) = sum_a U_a(cy, cz) h_a(cx, ux),
     // contracted axis by axis (z, then y, then x)
     const Basis1D bx(uxf), by(uyf), bz(uzf);
@@ -733,7 +755,7 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
     // rest population
     {
         const float w = wgt(0);
-        const float de = (float)(E0 - 1.5 * wgtd(0) * rho * u2d - 3.0 * nub * udr);
+        const float de = (float)E0 - 1.5f * w * rhof * u2 - 3.f * nubf * udr;
         const float Fp = -3.f * w * uF;
         const float pert = on ? k.A * (10.f / 27.f) * gn : 0.f;
         const float delta = U0[1][1] * bx.h0[1] + U1[1][1] * bx.h1[1] + U2[1][1] * h2(0);
@@ -782,8 +804,8 @@ __global__ __launch_bounds__(BLOCK) void k_collide(const typename S::T* __restri
     pull_all<S, false>(src, k, nd.n, d, unused);
     const float phic = ldp(PD, nd.n).x;
     const float xr = ldp(XR, nd.n);
-    double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    gradients(PD, k, nd.n, g);
+    float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    gradients_f(PD, k, nd.n, g);
     collide_store<BC, S>(k, nd, d, phic, xr, g, dst, Rout);
 }
 
@@ -802,8 +824,8 @@ __global__ __launch_bounds__(BLOCK) void k_outlet_collide(const float* __restric
     for (int i = 0; i < Q; ++i) d[i] = hcur[(size_t)i * k.plane + nd.q];
     const float phic = ldp(PD, nd.n).x;
     const float xr = ldp(XR, nd.n);
-    double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    gradients(PD, k, nd.n, g);
+    float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    gradients_f(PD, k, nd.n, g);
     collide_store<LBM_BC_JET, S>(k, nd, d, phic, xr, g, dst, Rout);
 }
 

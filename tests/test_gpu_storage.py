@@ -1,0 +1,87 @@
+"""16-bit population storage (BF16 / FP16 deviations f_i - w_i rho_b0, FP32
+arithmetic) through the C ABI.
+
+* Codec: a state written with lbm_set_state is stored as the deviation d and
+  the red populations rounded to the storage format; lbm_get_state returns
+  them decoded.  Checked bit for bit against torch's round-to-nearest-even
+  conversions (the library encodes with the gfx950 conversion instructions).
+* Error against the FP64 oracle, per field (rho, u, phi), for FP32, BF16 and
+  FP16 storage on a jet with the same boundaries, buoyancy and inlet noise as
+  the 128x128x512 workload, at steps 100 and 300.  Bound (the benchmark spec): the
+  velocity error of the 16-bit forms <= 1e-3 u_max.
+"""
+import numpy as np
+import pytest
+
+from harness import Q, gpu_fields, oracle_fields, oracle_init, random_state, rel_linf, say
+from paper_1804_08923_amd.workloads import Problem, jet_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible ROCm device"
+    return t
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_codec_round_trip(torch, orc, storage):
+    from paper_1804_08923_amd.lbm import LBM
+    prob = Problem(name="codec", nx=20, ny=13, nz=9, bc="periodic", rho_r0=1.0, rho_b0=0.5, nu_r=0.02,
+                   nu_b=0.05, A=2e-3, init="jet", storage=storage)
+    _, fr, fb, _ = random_state(orc, prob, seed=3, noise=2e-3)
+    st32 = np.concatenate([fr, fb]).astype(np.float32)
+    sim = LBM(prob)
+    sim.set_state(torch.from_numpy(st32).cuda(), t=0)
+    got = sim.get_state().cpu().numpy()
+    sim.close()
+    tdt = torch.bfloat16 if storage == "bf16" else torch.float16
+    w = np.asarray(orc.lattice()[1], np.float64)  # lattice weights in the velocity-set order
+    # red populations: the stored value is the RNE conversion of the FP32 input
+    fr_ref = torch.from_numpy(st32[:Q]).to(tdt).float().numpy()
+    assert np.array_equal(got[:Q], fr_ref), "red populations differ from torch's RNE conversion"
+    # deviation: d = fr + fb - w rho_b0 formed in FP64, rounded to FP32, then to the storage format
+    d32 = ((st32[:Q].astype(np.float64) + st32[Q:].astype(np.float64))
+           - w[:, None] * prob.rho_b0).astype(np.float32)
+    d_ref = torch.from_numpy(d32).to(tdt).float().numpy().astype(np.float64)
+    d_got = (got[:Q].astype(np.float64) + got[Q:].astype(np.float64)) - w[:, None] * prob.rho_b0
+    # get_state forms blue in FP64 and rounds it once to FP32
+    tol = 2.0 ** -24 * np.abs(got[Q:]).astype(np.float64) * 1.01
+    assert np.all(np.abs(d_got - d_ref) <= tol), np.abs(d_got - d_ref).max()
+    say(f"{storage}: codec matches torch RNE on {st32[:Q].size} red values and deviations")
+
+
+def test_storage_error_vs_oracle(torch, orc):
+    """Per-field error of FP32 / BF16 / FP16 storage against the FP64 oracle on
+    a 32x32x64 jet (gamma = 2, Re = 100, We = 30, Fr = 10, 1 % inlet noise)."""
+    from paper_1804_08923_amd.lbm import LBM
+    base = jet_problem("jet-32x32x64", 32, 32, 64, D=10, u=0.04, gamma=2.0, eta=1.0, Re=100.0, We=30.0,
+                       Fr=10.0, steps=300, noise_amp=0.01, noise_seed=20180423)
+    checkpoints = (100, 300)
+    p, fr, fb, h = oracle_init(orc, base)
+    ref = {}
+    done = 0
+    for s in checkpoints:
+        orc.step(p, base.A, fr, fb, h, done, s - done)
+        done = s
+        ref[s] = oracle_fields(orc, p, fr, fb)
+    report = {}
+    for storage in ("fp32", "bf16", "fp16"):
+        sim = LBM(base.replace(storage=storage))
+        done = 0
+        for s in checkpoints:
+            sim.step(s - done)
+            done = s
+            g = gpu_fields(sim)
+            umax = np.linalg.norm(ref[s]["u"], axis=1).max()
+            e = {f: rel_linf(g[f], ref[s][f]) for f in ("rho", "u", "phi")}
+            report[(storage, s)] = e
+            say(f"  {storage} step {s}: rel Linf rho {e['rho']:.2e} u {e['u']:.2e} (u_max {umax:.3e}) "
+                f"phi {e['phi']:.2e}")
+        sim.close()
+    for s in checkpoints:
+        assert report[("fp32", s)]["u"] < 1e-4
+        for st in ("bf16", "fp16"):
+            assert report[(st, s)]["u"] <= 1e-3, (st, s, report[(st, s)])
