@@ -27,14 +27,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Reference model of a step: both colour sets (2 x 27 populations) read once and
 # written once per node update.
-STEP_BYTES = {"fp32": 432, "bf16": 216, "fp16": 216}
+STEP_BYTES = {"fp32": 432, "bf16": 216, "fp16": 216, "bf16eq": 216, "fp16eq": 216}
 # Bytes this implementation must move per node update.  Fused kernel: 27
 # colour-blind deviations read, (phi, rho - rho_b0) and rho_r/rho read, 27
 # deviations and the float4 (rho_r/rho, V) of the recolouring written.  Density
 # pass: 27 deviations and the source-node float4 read, 3 floats written.
+# Equilibrium-referenced 16-bit forms: the rest population in two 16-bit
+# planes and a 16-byte reference record per node, read and written.
 FUSED_BYTES = {"fp32": 27 * 4 + 12 + 27 * 4 + 16, "bf16": 27 * 2 + 12 + 27 * 2 + 16,
-               "fp16": 27 * 2 + 12 + 27 * 2 + 16}
-DENSITY_BYTES = {"fp32": 27 * 4 + 16 + 12, "bf16": 27 * 2 + 16 + 12, "fp16": 27 * 2 + 16 + 12}
+               "fp16": 27 * 2 + 12 + 27 * 2 + 16, "bf16eq": 28 * 2 + 16 + 12 + 28 * 2 + 16 + 16,
+               "fp16eq": 28 * 2 + 16 + 12 + 28 * 2 + 16 + 16}
+DENSITY_BYTES = {"fp32": 27 * 4 + 16 + 12, "bf16": 27 * 2 + 16 + 12, "fp16": 27 * 2 + 16 + 12,
+                 "bf16eq": 28 * 2 + 16 + 16 + 12, "fp16eq": 28 * 2 + 16 + 16 + 12}
 PAPER_CONTEXT = {"mlups": [1.2, 12.0], "hardware": "unspecified cluster (COMA / Earth Simulator named)",
                  "workload": "240x240x1200 UT jet, 20000 iterations in ~32 h"}
 
@@ -206,7 +210,7 @@ def main():
         f"boundary {main_leg['boundary_ms']:.3f} ms")
     legs = {}
     if not args.no_legs:
-        for st in ("bf16", "fp16"):
+        for st in ("bf16", "fp16", "bf16eq", "fp16eq"):
             r = run_leg(prob.replace(storage=st), args.steps, args.warmup)
             legs[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                         "x_fp32": round(r["mlups"] / main_leg["mlups"], 3),

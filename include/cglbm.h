@@ -46,7 +46,23 @@ extern "C" {
 #define LBM_ERR_STATE (-5)       /* call out of order (e.g. step before init) */
 
 enum lbm_bc { LBM_BC_PERIODIC = 0, LBM_BC_JET = 1 };
-enum lbm_storage { LBM_STORAGE_FP32 = 0, LBM_STORAGE_BF16 = 1, LBM_STORAGE_FP16 = 2 };
+/* Population storage (arithmetic is FP32 in every form; not in the paper):
+ *   FP32     the colour-blind deviations d_i = f_i - w_i rho_b0 in FP32;
+ *   BF16     the same deviations in bfloat16 (round to nearest even);
+ *   FP16     the same deviations in IEEE binary16;
+ *   BF16_EQ, FP16_EQ  equilibrium-referenced 16-bit forms: moving directions
+ *            store d_i minus the phase and velocity parts of a per-node
+ *            reference equilibrium (rho~, u~, rho kappa - rho_b0, rounded to
+ *            the format and stored beside them), the rest population is
+ *            kept exactly; slower, but the momentum no longer carries the
+ *            16-bit rounding of the equilibrium. */
+enum lbm_storage {
+    LBM_STORAGE_FP32 = 0,
+    LBM_STORAGE_BF16 = 1,
+    LBM_STORAGE_FP16 = 2,
+    LBM_STORAGE_BF16_EQ = 3,
+    LBM_STORAGE_FP16_EQ = 4
+};
 enum lbm_init_kind {
     LBM_INIT_FIELDS = 0,  /* per-colour equilibria of caller fields rho_r, rho_b, u */
     LBM_INIT_DROPLET = 1, /* tanh droplet of Sec. III at rest */
@@ -81,7 +97,8 @@ typedef struct lbm_sizes {
     uint64_t n_nodes;
     uint64_t pop_bytes;     /* each of the two population buffers (A and B): 54 planes of
                                (nx+2)(ny+2)(nz+2) padded nodes in the storage format */
-    uint64_t field_bytes;   /* per-node fields and recolouring scalars: 11 floats per padded node */
+    uint64_t field_bytes;   /* per-node fields and recolouring scalars: 11 floats per padded node
+                               (19 with the reference records of BF16_EQ / FP16_EQ) */
     uint64_t hist_bytes;    /* outlet planes of the previous and current step, 2 x 54 floats
                                per (x, y); jet only */
     uint64_t audit_bytes;   /* FP64 partial sums of the audit reduction */

@@ -18,6 +18,7 @@ struct lbm_handle {
     void* pop[2];
     int cur;            // population buffer holding the current state
     float4* R[2];       // (rho_r/rho, V) written together with pop[0] resp. pop[1]
+    uint4* Qr[2];       // referenced 16-bit storage: reference records written with pop[0] resp. pop[1]
     float2* PD;         // (phi, rho - rho_b0) per padded node
     float* XR;          // rho_r / rho per padded node
     float* hist[2];     // outlet plane (jet): [hprev] previous step, [hprev ^ 1] current
@@ -66,6 +67,11 @@ int fail(int code, const char* fmt, ...)
 
 size_t elem_bytes(int storage) { return storage == LBM_STORAGE_FP32 ? 4 : 2; }
 
+bool eq_ref(int storage) { return storage == LBM_STORAGE_BF16_EQ || storage == LBM_STORAGE_FP16_EQ; }
+
+// floats per padded node of the field buffer: R (x2), [reference records (x2)], PD, XR
+uint64_t field_floats(int storage) { return eq_ref(storage) ? 19 : 11; }
+
 uint64_t padded_nodes(const lbm_params* p)
 {
     return (uint64_t)(p->nx + 2) * (uint64_t)(p->ny + 2) * (uint64_t)(p->nz + 2);
@@ -75,7 +81,7 @@ int validate(const lbm_params* p)
 {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
     if (p->bc != LBM_BC_PERIODIC && p->bc != LBM_BC_JET) return fail(LBM_ERR_INVALID_ARG, "unknown bc %d", p->bc);
-    if (p->storage < LBM_STORAGE_FP32 || p->storage > LBM_STORAGE_FP16)
+    if (p->storage < LBM_STORAGE_FP32 || p->storage > LBM_STORAGE_FP16_EQ)
         return fail(LBM_ERR_INVALID_ARG, "unknown storage %d", p->storage);
     const int minn = p->bc == LBM_BC_JET ? 3 : 1;
     if (p->nx < minn || p->ny < minn || p->nz < minn)
@@ -164,11 +170,15 @@ int dispatch(int bc, int storage, F&& f)
     if (bc == LBM_BC_PERIODIC) {
         if (storage == LBM_STORAGE_FP32) return f(IntC<LBM_BC_PERIODIC>{}, StF32{});
         if (storage == LBM_STORAGE_BF16) return f(IntC<LBM_BC_PERIODIC>{}, StBF16{});
-        return f(IntC<LBM_BC_PERIODIC>{}, StF16{});
+        if (storage == LBM_STORAGE_FP16) return f(IntC<LBM_BC_PERIODIC>{}, StF16{});
+        if (storage == LBM_STORAGE_BF16_EQ) return f(IntC<LBM_BC_PERIODIC>{}, StBF16Eq{});
+        return f(IntC<LBM_BC_PERIODIC>{}, StF16Eq{});
     }
     if (storage == LBM_STORAGE_FP32) return f(IntC<LBM_BC_JET>{}, StF32{});
     if (storage == LBM_STORAGE_BF16) return f(IntC<LBM_BC_JET>{}, StBF16{});
-    return f(IntC<LBM_BC_JET>{}, StF16{});
+    if (storage == LBM_STORAGE_FP16) return f(IntC<LBM_BC_JET>{}, StF16{});
+    if (storage == LBM_STORAGE_BF16_EQ) return f(IntC<LBM_BC_JET>{}, StBF16Eq{});
+    return f(IntC<LBM_BC_JET>{}, StF16Eq{});
 }
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
@@ -180,6 +190,7 @@ KP read_kp(const lbm_handle* h)
     k.t = h->t;
     k.unshifted = h->unshifted;
     k.R = h->R[h->cur];
+    k.Qrec = h->Qr[h->cur];
     k.z0 = 0;
     return k;
 }
@@ -199,7 +210,7 @@ int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
     const uint64_t nblk = ((plane + BLOCK - 1) / BLOCK) * (uint64_t)p->nz;
     out->n_nodes = N;
     out->pop_bytes = 2ull * Q * NP * elem_bytes(p->storage);
-    out->field_bytes = 11ull * NP * sizeof(float);
+    out->field_bytes = field_floats(p->storage) * NP * sizeof(float);
     out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * 2ull * Q * plane * sizeof(float) : 0;
     out->audit_bytes = (nblk + 1) * 5 * sizeof(double);
     out->inlet_bytes = plane * sizeof(float);
@@ -235,8 +246,11 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->cur = 0;
     H->R[0] = (float4*)buf->fields;
     H->R[1] = (float4*)(buf->fields + 4 * NP);
-    H->PD = (float2*)(buf->fields + 8 * NP);
-    H->XR = buf->fields + 10 * NP;
+    const size_t qf = eq_ref(p->storage) ? 8 * NP : 0;  // records after R, 16-byte aligned
+    H->Qr[0] = eq_ref(p->storage) ? (uint4*)(buf->fields + 8 * NP) : nullptr;
+    H->Qr[1] = eq_ref(p->storage) ? (uint4*)(buf->fields + 12 * NP) : nullptr;
+    H->PD = (float2*)(buf->fields + 8 * NP + qf);
+    H->XR = buf->fields + 10 * NP + qf;
     const size_t hplane = 2 * (size_t)Q * H->k.plane;
     H->hist[0] = p->bc == LBM_BC_JET ? buf->hist : nullptr;
     H->hist[1] = p->bc == LBM_BC_JET ? buf->hist + hplane : nullptr;
@@ -288,6 +302,7 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
             const T* src = (const T*)h->pop[h->cur];
             T* dst = (T*)h->pop[h->cur ^ 1];
             float4* Rout = h->R[h->cur ^ 1];
+            uint4* Qout = h->Qr[h->cur ^ 1];
             float* hprev = h->hist[h->hprev];
             float* hcur = h->hist[h->hprev ^ 1];
             hipEvent_t* e = nullptr;
@@ -315,15 +330,15 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
             if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
             // fused collide-perturb-recolour-stream
             hipLaunchKernelGGL((k_collide<BC, S>), h->grid_bulk, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,
-                               Rout, k);
+                               Rout, Qout, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[3], h->stream));
             if (jet) {
                 hipLaunchKernelGGL(k_outlet_collide<S>, h->grid_plane, dim3(BLOCK), 0, h->stream, hcur, dst, h->PD,
-                                   h->XR, Rout, ko);
+                                   h->XR, Rout, Qout, ko);
                 LAUNCH_CHECK();
             }
-            hipLaunchKernelGGL((k_pop_ghosts<BC, S>), h->grid_shell, dim3(BLOCK), 0, h->stream, dst, Rout, k,
+            hipLaunchKernelGGL((k_pop_ghosts<BC, S>), h->grid_shell, dim3(BLOCK), 0, h->stream, dst, Rout, Qout, k,
                                h->ncells);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[4], h->stream));

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK = 0
 BC = {"periodic": 0, "jet": 1}
-STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16eq": 3, "fp16eq": 4}
 INIT = {"fields": 0, "droplet": 1, "jet": 2}
 Q = 27
 

@@ -47,7 +47,7 @@ class Problem:
     drop_W: float = 2.0
     drop_center: Optional[Tuple[float, float, float]] = None
     steps: int = 200
-    storage: str = "fp32"         # "fp32" | "bf16" | "fp16"
+    storage: str = "fp32"         # "fp32" | "bf16" | "fp16" | "bf16eq" | "fp16eq"
     meta: dict = field(default_factory=dict)
 
     @property

@@ -45,8 +45,10 @@ def test_query_sizes(lib):
         assert s.state_bytes == 54 * N * 4
         assert s.field_bytes == 44 * NP
         assert s.hist_bytes == (2 * 54 * prob.nx * prob.ny * 4 if prob.bc == "jet" else 0)
-        for st, b in (("bf16", 2), ("fp16", 2)):
-            assert lbm.lbm_query_sizes(lbm.make_params(prob.replace(storage=st))).pop_bytes == 54 * NP * b
+        for st, b, fb in (("bf16", 2, 44), ("fp16", 2, 44), ("bf16eq", 2, 76), ("fp16eq", 2, 76)):
+            s2 = lbm.lbm_query_sizes(lbm.make_params(prob.replace(storage=st)))
+            assert s2.pop_bytes == 54 * NP * b
+            assert s2.field_bytes == fb * NP
 
 
 @pytest.mark.parametrize("field,value,code", [
