@@ -151,7 +151,7 @@ def adjoint_leg(prob, nadj=10):
     return dict(adjoint_ms=adj_ms, recompute_ms=rec_ms, finite=finite)
 
 
-def cpu_baseline(prob, nz_sample=64, steps=8):
+def cpu_baseline(prob, nz_sample=64, steps=32):
     """The FP64 oracle on a slab of the same jet (full cross-section, nz_sample planes)."""
     from oracle import Oracle
     from oracle import make_params as or_params
