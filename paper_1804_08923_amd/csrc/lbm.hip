@@ -30,6 +30,7 @@ struct lbm_handle {
     int unshifted;      // current buffer holds a general state at the node itself
     dim3 grid_all;      // every interior plane
     dim3 grid_bulk;     // planes handled by the bulk kernels (jet: without the outlet plane)
+    dim3 grid_tiles;    // stencil tiles of the bulk planes (density pass, fused collision)
     dim3 grid_plane;    // one plane
     dim3 grid_shell;    // ghost shell cells
     uint32_t ncells;    // ghost shell cell count
@@ -130,6 +131,7 @@ void fill_kp(const lbm_params* p, const float* inlet, KP* k)
     k->nx_mul = (uint32_t)((two + (unsigned long long)p->nx - 1) / (unsigned long long)p->nx);
     k->nx_sh = 31 + L;
     k->z0 = 0;
+    k->ntx = (p->nx + STX - 1) / STX;
     const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
     k->rho_r0 = (float)p->rho_r0;
     k->rho_b0 = (float)p->rho_b0;
@@ -264,6 +266,7 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->grid_all = dim3(bx, p->nz);
     H->grid_bulk = dim3(bx, p->bc == LBM_BC_JET ? p->nz - 1 : p->nz);
     H->grid_plane = dim3(bx, 1);
+    H->grid_tiles = dim3((unsigned)(H->k.ntx * ((p->ny + STY - 1) / STY)), H->grid_bulk.y);
     const uint64_t cells = 2ull * H->k.px * H->k.py + 2ull * H->k.px * p->nz + 2ull * p->ny * p->nz;
     H->ncells = (uint32_t)cells;
     H->grid_shell = dim3((unsigned)((cells + BLOCK - 1) / BLOCK));
@@ -317,7 +320,7 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
                 HIP_CHECK(hipEventRecord(e[0], h->stream));
             }
             // density pass
-            hipLaunchKernelGGL(k_density<S>, h->grid_bulk, dim3(BLOCK), 0, h->stream, src, h->PD, h->XR, k);
+            hipLaunchKernelGGL(k_density<S>, h->grid_tiles, dim3(BLOCK), 0, h->stream, src, h->PD, h->XR, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
             if (jet) {
@@ -329,7 +332,7 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
             // fused collide-perturb-recolour-stream
-            hipLaunchKernelGGL((k_collide<BC, S>), h->grid_bulk, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,
+            hipLaunchKernelGGL((k_collide<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,
                                Rout, Qout, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[3], h->stream));

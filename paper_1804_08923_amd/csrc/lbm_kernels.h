@@ -101,6 +101,7 @@ struct KP {
     uint32_t plane;    // nx * ny
     uint32_t nx_mul;   // p / nx = (p * nx_mul) >> nx_sh, exact for p < 2^31
     int nx_sh;
+    int ntx;           // stencil tiles (STX wide) along x
     int z0;            // interior plane of blockIdx.y = 0
     float rho_r0, rho_b0, alpha_r, alpha_b;
     float dalpha;      // alpha_r - alpha_b
@@ -401,6 +402,58 @@ __device__ void block_partials(double (&v)[NV], double* __restrict__ out, uint32
 
 constexpr int BLOCK = 256;
 
+// ---------------------------------------------------------------- stencil tiles
+// The two stencil kernels (density pass, fused collision) take a tile of
+// STX x STY nodes of one plane per block and stage the neighbour data they
+// gather 26 times per node (the recolouring float4 R of the density pass, the
+// (phi, rho) fields of the gradient) once into LDS: a window of the tile plus a
+// one-node rim in x and y, over planes z - 1, z, z + 1, loaded row by row.
+constexpr int STX = 128, STY = BLOCK / STX;
+constexpr int SWX = STX + 2, SWY = STY + 2, SW = 3 * SWX * SWY;
+
+struct Tile {
+    int x0, y0, z, lx, ly;
+    Node nd;
+};
+
+__device__ __forceinline__ Tile this_tile(const KP& k)
+{
+    Tile t;
+    const int ty = (int)blockIdx.x / k.ntx, tx = (int)blockIdx.x - ty * k.ntx;
+    t.x0 = tx * STX;
+    t.y0 = ty * STY;
+    t.z = (int)blockIdx.y + k.z0;
+    t.lx = (int)threadIdx.x % STX;
+    t.ly = (int)threadIdx.x / STX;
+    Node& d = t.nd;
+    d.x = t.x0 + t.lx;
+    d.y = t.y0 + t.ly;
+    d.z = t.z;
+    d.valid = d.x < k.nx && d.y < k.ny;
+    d.q = (uint32_t)d.y * (uint32_t)k.nx + (uint32_t)d.x;
+    d.n = pidx(k, d.x, d.y, d.z);
+    return t;
+}
+
+// window slot of the node at offset (dx, dy, dz) from local node (lx, ly)
+__device__ __forceinline__ int wslot(int lx, int ly, int dx, int dy, int dz)
+{
+    return ((dz + 1) * SWY + (ly + 1 + dy)) * SWX + (lx + 1 + dx);
+}
+
+// stage field f over the window of tile t (padded cells beyond the ghost
+// shell of a ragged last tile are skipped: no valid node reads them)
+template <class T>
+__device__ __forceinline__ void load_window(T* __restrict__ win, const T* __restrict__ f, const KP& k, const Tile& t)
+{
+    for (int w = threadIdx.x; w < SW; w += BLOCK) {
+        const int wx = w % SWX, r = w / SWX;
+        const int wy = r % SWY, wz = r / SWY;
+        const int x = t.x0 - 1 + wx, y = t.y0 - 1 + wy;
+        if (x <= k.nx && y <= k.ny) win[w] = ldp(f, pidx(k, x, y, t.z - 1 + wz));
+    }
+}
+
 // ---------------------------------------------------------------- density pass
 // fields: PD = (phi, rho - rho_b0) per padded node, XR = rho_r / rho.
 __device__ __forceinline__ void store_fields(float2* __restrict__ PD, float* __restrict__ XR, const KP& k, uint32_t n,
@@ -465,20 +518,49 @@ __device__ __forceinline__ void store_fields_sums(float2* __restrict__ PD, float
     stp(XR, n, (float)(rr / rho));
 }
 
+// the shifted-state sums of accum_density from pulled deviations d and R read
+// from the LDS window
+template <int I = 0>
+__device__ __forceinline__ void accum_density_win(const KP& k, const float* d, const float4* __restrict__ win,
+                                                  int lx, int ly, double& m0, float& xr0, float& corr)
+{
+    if constexpr (I < Q) {
+        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
+        const float4 r = win[wslot(lx, ly, -cx, -cy, -cz)];
+        m0 += (double)d[I];
+        if (I == 0) {
+            xr0 = r.x;
+        } else {
+            corr += (r.x - xr0) * (d[I] + wgt(I) * k.rho_b0) +
+                    (wgt(I) * inv_len(I)) * (cx * r.y + cy * r.z + cz * r.w);
+        }
+        accum_density_win<I + 1>(k, d, win, lx, ly, m0, xr0, corr);
+    }
+}
+
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
                                                     float* __restrict__ XR, KP k)
 {
-    const Node nd = this_node(k);
-    if (!nd.valid) return;
+    __shared__ float4 win[SW];
+    const Tile t = this_tile(k);
+    const Node& nd = t.nd;
     double m0 = 0.0, rr = 0.0;
-    float xr0 = 0.f, corr = 0.f;
     if (k.unshifted) {
+        if (!nd.valid) return;
+        float xr0 = 0.f, corr = 0.f;
         accum_density<S, false>(src, k, nd.n, m0, rr, xr0, corr);
-    } else {
-        accum_density<S, true>(src, k, nd.n, m0, rr, xr0, corr);
-        rr = (double)xr0 * ((double)k.rho_b0 + m0) + (double)corr;
+        store_fields_sums(PD, XR, k, nd.n, m0, rr);
+        return;
     }
+    load_window(win, k.R, k, t);
+    __syncthreads();
+    if (!nd.valid) return;
+    float d[Q], unused[Q];
+    pull_dirs<S, false, true>(src, k, nd.n, d, unused);
+    float xr0 = 0.f, corr = 0.f;
+    accum_density_win(k, d, win, t.lx, t.ly, m0, xr0, corr);
+    rr = (double)xr0 * ((double)k.rho_b0 + m0) + (double)corr;
     store_fields_sums(PD, XR, k, nd.n, m0, rr);
 }
 
@@ -663,6 +745,23 @@ __device__ __forceinline__ void gradients_f(const float2* __restrict__ pd, const
         if (cy) { g[1] += (w3 * cy) * dp; g[4] += (w3 * cy) * dr; }
         if (cz) { g[2] += (w3 * cz) * dp; g[5] += (w3 * cz) * dr; }
         gradients_f<I + 2>(pd, k, n, g);
+    }
+}
+
+// the same FP32 gradients from the LDS window of the (phi, rho) fields
+template <int I = 1>
+__device__ __forceinline__ void gradients_win(const float2* __restrict__ win, int lx, int ly, float (&g)[6])
+{
+    if constexpr (I < Q) {
+        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
+        const float2 a = win[wslot(lx, ly, cx, cy, cz)];
+        const float2 b = win[wslot(lx, ly, -cx, -cy, -cz)];
+        const float dp = a.x - b.x, dr = a.y - b.y;
+        constexpr float w3 = 3.0f * wgt(I);
+        if (cx) { g[0] += (w3 * cx) * dp; g[3] += (w3 * cx) * dr; }
+        if (cy) { g[1] += (w3 * cy) * dp; g[4] += (w3 * cy) * dr; }
+        if (cz) { g[2] += (w3 * cz) * dp; g[5] += (w3 * cz) * dr; }
+        gradients_win<I + 2>(win, lx, ly, g);
     }
 }
 
@@ -939,14 +1038,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
                                                     const float* __restrict__ XR, float4* __restrict__ Rout,
                                                     uint4* __restrict__ Qout, KP k)
 {
-    const Node nd = this_node(k);
+    // FP32 storage: the (phi, rho) stencil from an LDS window (measured faster);
+    // 16-bit storage: from the caches (the window barrier measured slower there)
+    constexpr bool kWin = sizeof(typename S::T) == 4;
+    __shared__ float2 win[kWin ? SW : 1];
+    const Tile t = this_tile(k);
+    const Node& nd = t.nd;
+    if constexpr (kWin) {
+        load_window(win, PD, k, t);
+        __syncthreads();
+    }
     if (!nd.valid) return;
     float d[Q], unused[Q];
     pull_all<S, false>(src, k, nd.n, d, unused);
-    const float phic = ldp(PD, nd.n).x;
     const float xr = ldp(XR, nd.n);
     float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    gradients_f(PD, k, nd.n, g);
+    float phic;
+    if constexpr (kWin) {
+        phic = win[wslot(t.lx, t.ly, 0, 0, 0)].x;
+        gradients_win(win, t.lx, t.ly, g);
+    } else {
+        phic = ldp(PD, nd.n).x;
+        gradients_f(PD, k, nd.n, g);
+    }
     collide_store<BC, S>(k, nd, d, phic, xr, g, dst, Rout, Qout);
 }
 
