@@ -188,7 +188,7 @@ int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float
 
 /* Instrumentation: with enable != 0, lbm_step records HIP events on its
  * stream around its kernel groups (density pass; fused collide-recolour-
- * stream kernel; boundary kernels: jet outlet plane and ghost-shell fills);
+ * stream kernel; boundary kernels: ghost-shell fills);
  * enable == 0 stops recording. */
 int lbm_profile(lbm_handle* h, int enable);
 

@@ -29,7 +29,6 @@ struct lbm_handle {
     long long t;        // time level of the current state
     int unshifted;      // current buffer holds a general state at the node itself
     dim3 grid_all;      // every interior plane
-    dim3 grid_bulk;     // planes handled by the bulk kernels (jet: without the outlet plane)
     dim3 grid_tiles;    // stencil tiles of the bulk planes (density pass, fused collision)
     dim3 grid_plane;    // one plane
     dim3 grid_shell;    // ghost shell cells
@@ -264,9 +263,8 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->unshifted = 1;
     const unsigned bx = (H->k.plane + BLOCK - 1) / BLOCK;
     H->grid_all = dim3(bx, p->nz);
-    H->grid_bulk = dim3(bx, p->bc == LBM_BC_JET ? p->nz - 1 : p->nz);
     H->grid_plane = dim3(bx, 1);
-    H->grid_tiles = dim3((unsigned)(H->k.ntx * ((p->ny + STY - 1) / STY)), H->grid_bulk.y);
+    H->grid_tiles = dim3((unsigned)(H->k.ntx * ((p->ny + STY - 1) / STY)), p->nz);
     const uint64_t cells = 2ull * H->k.px * H->k.py + 2ull * H->k.px * p->nz + 2ull * p->ny * p->nz;
     H->ncells = (uint32_t)cells;
     H->grid_shell = dim3((unsigned)((cells + BLOCK - 1) / BLOCK));
@@ -300,8 +298,6 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
         constexpr bool jet = BC == LBM_BC_JET;
         for (int s = 0; s < n_steps; ++s) {
             KP k = read_kp(h);
-            KP ko = k;
-            ko.z0 = h->p.nz - 1;
             const T* src = (const T*)h->pop[h->cur];
             T* dst = (T*)h->pop[h->cur ^ 1];
             float4* Rout = h->R[h->cur ^ 1];
@@ -319,28 +315,19 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
                 h->ev_used += 5;
                 HIP_CHECK(hipEventRecord(e[0], h->stream));
             }
-            // density pass
-            hipLaunchKernelGGL(k_density<S>, h->grid_tiles, dim3(BLOCK), 0, h->stream, src, h->PD, h->XR, k);
+            // density pass (jet: the outlet plane by the convective condition)
+            hipLaunchKernelGGL((k_density<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, h->PD, h->XR,
+                               hprev, hcur, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
-            if (jet) {
-                hipLaunchKernelGGL(k_outlet_density<S>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->PD,
-                                   h->XR, hprev, hcur, ko);
-                LAUNCH_CHECK();
-            }
             hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
             // fused collide-perturb-recolour-stream
             hipLaunchKernelGGL((k_collide<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,
-                               Rout, Qout, k);
+                               hcur, Rout, Qout, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[3], h->stream));
-            if (jet) {
-                hipLaunchKernelGGL(k_outlet_collide<S>, h->grid_plane, dim3(BLOCK), 0, h->stream, hcur, dst, h->PD,
-                                   h->XR, Rout, Qout, ko);
-                LAUNCH_CHECK();
-            }
             hipLaunchKernelGGL((k_pop_ghosts<BC, S>), h->grid_shell, dim3(BLOCK), 0, h->stream, dst, Rout, Qout, k,
                                h->ncells);
             LAUNCH_CHECK();

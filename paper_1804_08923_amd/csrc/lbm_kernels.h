@@ -538,13 +538,28 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
     }
 }
 
-template <class S>
+// Jet: the blocks of the outlet plane (z = nz - 1) take its state from the
+// convective condition instead and record it in hcur for the collision.
+template <int BC, class S>
 __global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
-                                                    float* __restrict__ XR, KP k)
+                                                    float* __restrict__ XR, const float* __restrict__ hprev,
+                                                    float* __restrict__ hcur, KP k)
 {
     __shared__ float4 win[SW];
     const Tile t = this_tile(k);
     const Node& nd = t.nd;
+    if (BC == LBM_BC_JET && t.z == k.nz - 1) {
+        if (!nd.valid) return;
+        float d[Q], fr[Q];
+        outlet_state<S>(src, k, hprev, nd, d, fr);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            hcur[(size_t)i * k.plane + nd.q] = d[i];
+            hcur[(size_t)(Q + i) * k.plane + nd.q] = fr[i];
+        }
+        store_fields(PD, XR, k, nd.n, d, fr);
+        return;
+    }
     double m0 = 0.0, rr = 0.0;
     if (k.unshifted) {
         if (!nd.valid) return;
@@ -564,24 +579,6 @@ __global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restri
     store_fields_sums(PD, XR, k, nd.n, m0, rr);
 }
 
-// jet outlet plane: convective condition, records the plane in hcur
-template <class S>
-__global__ __launch_bounds__(BLOCK) void k_outlet_density(const typename S::T* __restrict__ src,
-                                                           float2* __restrict__ PD, float* __restrict__ XR,
-                                                           const float* __restrict__ hprev,
-                                                           float* __restrict__ hcur, KP k)
-{
-    const Node nd = this_node(k);
-    if (!nd.valid) return;
-    float d[Q], fr[Q];
-    outlet_state<S>(src, k, hprev, nd, d, fr);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        hcur[(size_t)i * k.plane + nd.q] = d[i];
-        hcur[(size_t)(Q + i) * k.plane + nd.q] = fr[i];
-    }
-    store_fields(PD, XR, k, nd.n, d, fr);
-}
 
 // ---------------------------------------------------------------- ghost shell
 // Ghost cell g of the shell: z faces (all x, y incl. ghosts), then y faces
@@ -1031,12 +1028,13 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
 
 // ---------------------------------------------------------------- fused collide-recolour-stream
 // three waves per SIMD: measured faster on MI355X than the four the register
-// count would allow (fewer concurrent streams contend for the caches)
+// count would allow (fewer concurrent streams contend for the caches).  Jet:
+// the outlet plane's pre-collision state is the one the density pass recorded.
 template <int BC, class S>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_collide(const typename S::T* __restrict__ src,
-                                                    typename S::T* __restrict__ dst, const float2* __restrict__ PD,
-                                                    const float* __restrict__ XR, float4* __restrict__ Rout,
-                                                    uint4* __restrict__ Qout, KP k)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_collide(
+    const typename S::T* __restrict__ src, typename S::T* __restrict__ dst, const float2* __restrict__ PD,
+    const float* __restrict__ XR, const float* __restrict__ hcur, float4* __restrict__ Rout, uint4* __restrict__ Qout,
+    KP k)
 {
     // FP32 storage: the (phi, rho) stencil from an LDS window (measured faster);
     // 16-bit storage: from the caches (the window barrier measured slower there)
@@ -1049,8 +1047,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
         __syncthreads();
     }
     if (!nd.valid) return;
-    float d[Q], unused[Q];
-    pull_all<S, false>(src, k, nd.n, d, unused);
+    float d[Q];
+    if (BC == LBM_BC_JET && t.z == k.nz - 1) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = hcur[(size_t)i * k.plane + nd.q];
+    } else {
+        float unused[Q];
+        pull_all<S, false>(src, k, nd.n, d, unused);
+    }
     const float xr = ldp(XR, nd.n);
     float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float phic;
@@ -1064,25 +1068,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
     collide_store<BC, S>(k, nd, d, phic, xr, g, dst, Rout, Qout);
 }
 
-// jet outlet plane: the pre-collision state was recorded by k_outlet_density
-template <class S>
-__global__ __launch_bounds__(BLOCK) void k_outlet_collide(const float* __restrict__ hcur,
-                                                           typename S::T* __restrict__ dst,
-                                                           const float2* __restrict__ PD,
-                                                           const float* __restrict__ XR, float4* __restrict__ Rout,
-                                                           uint4* __restrict__ Qout, KP k)
-{
-    const Node nd = this_node(k);
-    if (!nd.valid) return;
-    float d[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = hcur[(size_t)i * k.plane + nd.q];
-    const float phic = ldp(PD, nd.n).x;
-    const float xr = ldp(XR, nd.n);
-    float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    gradients_f(PD, k, nd.n, g);
-    collide_store<LBM_BC_JET, S>(k, nd, d, phic, xr, g, dst, Rout, Qout);
-}
 
 // ---------------------------------------------------------------- state in and out
 // Initial state (general form): per-colour equilibria f^k_i = rho_k {varphi_i(alpha_k)
