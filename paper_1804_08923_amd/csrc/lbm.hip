@@ -29,7 +29,8 @@ struct lbm_handle {
     long long t;        // time level of the current state
     int unshifted;      // current buffer holds a general state at the node itself
     dim3 grid_all;      // every interior plane
-    dim3 grid_tiles;    // stencil tiles of the bulk planes (density pass, fused collision)
+    dim3 grid_tiles;    // stencil tiles of the fused collision
+    dim3 grid_dtiles;   // stencil tiles of the density pass
     dim3 grid_plane;    // one plane
     dim3 grid_shell;    // ghost shell cells
     uint32_t ncells;    // ghost shell cell count
@@ -265,6 +266,7 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->grid_all = dim3(bx, p->nz);
     H->grid_plane = dim3(bx, 1);
     H->grid_tiles = dim3((unsigned)(H->k.ntx * ((p->ny + STY - 1) / STY)), p->nz);
+    H->grid_dtiles = dim3((unsigned)(H->k.ntx * ((p->ny + DTY - 1) / DTY)), p->nz);
     const uint64_t cells = 2ull * H->k.px * H->k.py + 2ull * H->k.px * p->nz + 2ull * p->ny * p->nz;
     H->ncells = (uint32_t)cells;
     H->grid_shell = dim3((unsigned)((cells + BLOCK - 1) / BLOCK));
@@ -316,7 +318,7 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
                 HIP_CHECK(hipEventRecord(e[0], h->stream));
             }
             // density pass (jet: the outlet plane by the convective condition)
-            hipLaunchKernelGGL((k_density<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, h->PD, h->XR,
+            hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR,
                                hprev, hcur, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
@@ -441,7 +443,7 @@ int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float
         hipLaunchKernelGGL(k_adj_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, k,
                            h->ncells);
         LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_adj_fields<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, h->PD,
+        hipLaunchKernelGGL(k_adj_fields<BC>, h->grid_tiles, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, h->PD,
                            h->XR, w.DL, w.LC, lambda_out, k);
         LAUNCH_CHECK();
         if (BC == LBM_BC_JET && dJ_du_in) {

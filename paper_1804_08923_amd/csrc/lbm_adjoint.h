@@ -260,6 +260,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     const float2* __restrict__ PD, const float* __restrict__ XR, float* __restrict__ LC, float4* __restrict__ AG0,
     float4* __restrict__ AG1, double* __restrict__ AP, KP k)
 {
+    // the (phi, rho) stencil from the caches: an LDS window with its barrier
+    // measured slower at this kernel's two waves per SIMD
     const Node nd = this_node(k);
     double acc[1] = {0.0};
     if (nd.valid) {
@@ -328,14 +330,20 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fields(const float4* __restrict__
                                                        const float* __restrict__ XR, const float* __restrict__ DL,
                                                        const float* __restrict__ LC, float* __restrict__ lam_out, KP k)
 {
-    const Node nd = this_node(k);
+    // the stencil cotangents of the tile and its rim from LDS windows
+    __shared__ float4 w0[SW], w1[SW];
+    const Tile t = this_tile(k);
+    const Node& nd = t.nd;
+    load_window(w0, AG0, k, t);
+    load_window(w1, AG1, k, t);
+    __syncthreads();
     if (!nd.valid) return;
-    float Lphi = ldp(AG0, nd.n).w, Lrf = 0.f;
-    const float Lxr = ldp(AG1, nd.n).w;
+    float Lphi = w0[wslot(t.lx, t.ly, 0, 0, 0)].w, Lrf = 0.f;
+    const float Lxr = w1[wslot(t.lx, t.ly, 0, 0, 0)].w;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const uint32_t s = nd.n - (uint32_t)doff(k, kCX[i], kCY[i], kCZ[i]);
-        const float4 a0 = ldp(AG0, s), a1 = ldp(AG1, s);
+        const int ws = wslot(t.lx, t.ly, -kCX[i], -kCY[i], -kCZ[i]);
+        const float4 a0 = w0[ws], a1 = w1[ws];
         const float w3 = 3.f * wgt(i);
         Lphi += w3 * (kCX[i] * a0.x + kCY[i] * a0.y + kCZ[i] * a0.z);
         Lrf += w3 * (kCX[i] * a1.x + kCY[i] * a1.y + kCZ[i] * a1.z);

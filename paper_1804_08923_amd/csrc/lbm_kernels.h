@@ -409,6 +409,14 @@ constexpr int BLOCK = 256;
 // (phi, rho) fields of the gradient) once into LDS: a window of the tile plus a
 // one-node rim in x and y, over planes z - 1, z, z + 1, loaded row by row.
 constexpr int STX = 128, STY = BLOCK / STX;
+// the density pass takes 128 x 4 tiles (512 threads): measured faster than
+// 128 x 2 and 128 x 8 (less window rim per node, enough blocks per CU)
+constexpr int DTY = 4, DBLOCK = STX * DTY;
+
+template <int TY>
+struct TileShape {
+    static constexpr int WX = STX + 2, WY = TY + 2, W = 3 * WX * WY, NT = STX * TY;
+};
 constexpr int SWX = STX + 2, SWY = STY + 2, SW = 3 * SWX * SWY;
 
 struct Tile {
@@ -416,12 +424,13 @@ struct Tile {
     Node nd;
 };
 
+template <int TY = STY>
 __device__ __forceinline__ Tile this_tile(const KP& k)
 {
     Tile t;
     const int ty = (int)blockIdx.x / k.ntx, tx = (int)blockIdx.x - ty * k.ntx;
     t.x0 = tx * STX;
-    t.y0 = ty * STY;
+    t.y0 = ty * TY;
     t.z = (int)blockIdx.y + k.z0;
     t.lx = (int)threadIdx.x % STX;
     t.ly = (int)threadIdx.x / STX;
@@ -436,19 +445,21 @@ __device__ __forceinline__ Tile this_tile(const KP& k)
 }
 
 // window slot of the node at offset (dx, dy, dz) from local node (lx, ly)
+template <int TY = STY>
 __device__ __forceinline__ int wslot(int lx, int ly, int dx, int dy, int dz)
 {
-    return ((dz + 1) * SWY + (ly + 1 + dy)) * SWX + (lx + 1 + dx);
+    return ((dz + 1) * TileShape<TY>::WY + (ly + 1 + dy)) * TileShape<TY>::WX + (lx + 1 + dx);
 }
 
 // stage field f over the window of tile t (padded cells beyond the ghost
 // shell of a ragged last tile are skipped: no valid node reads them)
-template <class T>
+template <int TY = STY, class T>
 __device__ __forceinline__ void load_window(T* __restrict__ win, const T* __restrict__ f, const KP& k, const Tile& t)
 {
-    for (int w = threadIdx.x; w < SW; w += BLOCK) {
-        const int wx = w % SWX, r = w / SWX;
-        const int wy = r % SWY, wz = r / SWY;
+    using TS = TileShape<TY>;
+    for (int w = threadIdx.x; w < TS::W; w += TS::NT) {
+        const int wx = w % TS::WX, r = w / TS::WX;
+        const int wy = r % TS::WY, wz = r / TS::WY;
         const int x = t.x0 - 1 + wx, y = t.y0 - 1 + wy;
         if (x <= k.nx && y <= k.ny) win[w] = ldp(f, pidx(k, x, y, t.z - 1 + wz));
     }
@@ -526,7 +537,7 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
 {
     if constexpr (I < Q) {
         constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
-        const float4 r = win[wslot(lx, ly, -cx, -cy, -cz)];
+        const float4 r = win[wslot<DTY>(lx, ly, -cx, -cy, -cz)];
         m0 += (double)d[I];
         if (I == 0) {
             xr0 = r.x;
@@ -541,12 +552,12 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
 // Jet: the blocks of the outlet plane (z = nz - 1) take its state from the
 // convective condition instead and record it in hcur for the collision.
 template <int BC, class S>
-__global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
-                                                    float* __restrict__ XR, const float* __restrict__ hprev,
-                                                    float* __restrict__ hcur, KP k)
+__global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
+                                                     float* __restrict__ XR, const float* __restrict__ hprev,
+                                                     float* __restrict__ hcur, KP k)
 {
-    __shared__ float4 win[SW];
-    const Tile t = this_tile(k);
+    __shared__ float4 win[TileShape<DTY>::W];
+    const Tile t = this_tile<DTY>(k);
     const Node& nd = t.nd;
     if (BC == LBM_BC_JET && t.z == k.nz - 1) {
         if (!nd.valid) return;
@@ -568,7 +579,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(const typename S::T* __restri
         store_fields_sums(PD, XR, k, nd.n, m0, rr);
         return;
     }
-    load_window(win, k.R, k, t);
+    load_window<DTY>(win, k.R, k, t);
     __syncthreads();
     if (!nd.valid) return;
     float d[Q], unused[Q];
