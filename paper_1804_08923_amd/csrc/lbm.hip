@@ -17,7 +17,7 @@ struct lbm_handle {
     KP k;
     void* pop[2];
     int cur;            // population buffer holding the current state
-    float4* R[2];       // (rho_r/rho, V) written together with pop[0] resp. pop[1]
+    float4* R[2];       // (tagged minority fraction, V) written together with pop[0] resp. pop[1]
     uint4* Qr[2];       // referenced 16-bit storage: reference records written with pop[0] resp. pop[1]
     float2* PD;         // (phi, rho - rho_b0) per padded node
     float* XR;          // rho_r / rho per padded node
@@ -275,7 +275,7 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
         using S = decltype(st);
         (void)bc;
         const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
-        hipLaunchKernelGGL(k_init<S>, H->grid_all, dim3(BLOCK), 0, H->stream, (typename S::T*)H->pop[0], H->k,
+        hipLaunchKernelGGL(k_init<S>, H->grid_all, dim3(BLOCK), 0, H->stream, (typename S::T*)H->pop[0], H->R[0], H->k,
                            p->init, rho_r, rho_b, u, p->drop_cx, p->drop_cy, p->drop_cz, p->drop_R, p->drop_W,
                            p->rho_r0, p->rho_b0, ar, p->alpha_b, (double)H->k.rho_b0);
         LAUNCH_CHECK();
@@ -392,7 +392,7 @@ int lbm_set_state(lbm_handle* h, const float* state, int64_t t)
         using S = decltype(st);
         (void)bc;
         hipLaunchKernelGGL(k_set_state<S>, h->grid_all, dim3(BLOCK), 0, h->stream, (typename S::T*)h->pop[h->cur],
-                           k, state, (double)h->k.rho_b0);
+                           h->R[h->cur], k, state, (double)h->k.rho_b0);
         LAUNCH_CHECK();
         return LBM_OK;
     });

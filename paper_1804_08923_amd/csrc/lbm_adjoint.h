@@ -96,7 +96,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj_density(const float* __restrict__
         rr += a;
         M.add(i, (a + b) - wgtd(i) * (double)k.rho_b0);
     }
-    store_fields_sums(PD, XR, k, nd.n, M.m0, rr);
+    // the adjoint passes keep the red fraction x_r = rho_r/rho in XR
+    const double rho = (double)k.rho_b0 + M.m0;
+    store_pd(PD, k, nd.n, M.m0, rr, rho - rr);
+    stp(XR, nd.n, (float)(rr / rho));
     const double mv[10] = {M.m0, M.j[0], M.j[1], M.j[2], M.P[0], M.P[1], M.P[2], M.P[3], M.P[4], M.P[5]};
 #pragma unroll
     for (int a = 0; a < 10; ++a) MOM[(size_t)a * N + n] = (float)mv[a];

@@ -13,23 +13,27 @@
 //    small in both pure phases (rho_r0 varphi_i(alpha_r) = rho_b0 w_i for
 //    |c_i| >= 1 because gamma = (1 - alpha_b)/(1 - alpha_r)), so FP32 and
 //    16-bit storage keep the momentum sum_i d_i c_i well conditioned.
-//  * Red populations: after recolouring (Eqs. op3r/op3b) with
+//  * Colour populations: after recolouring (Eqs. op3r/op3b) with
 //    varphi_i = w_i kappa(alpha_bar) for |c_i| >= 1 and cos(theta_i) linear in
-//    c_i, the red post-collision populations are
-//        f^r*_i = (rho_r/rho) f'_i + (w_i / |c_i|) c_i . V,
-//        V = beta (rho_r rho_b / rho) kappa grad phi / |grad phi|,
-//    an affine function of the colour-blind post-collision f' with four
+//    c_i, the post-collision populations of either colour are
+//        f^r*_i = x_r f'_i + (w_i / |c_i|) c_i . V,   f^b*_i = x_b f'_i - (same),
+//        x_k = rho_k/rho,  V = beta (rho_r rho_b / rho) kappa grad phi / |grad phi|,
+//    affine functions of the colour-blind post-collision f' with four
 //    per-node scalars.  The fused kernel therefore stores only d' and the
-//    float4 R = (rho_r/rho, V) of every node; readers rebuild f^r of direction
-//    i at x from d_i and R at the source node x - c_i.  A general state (after
-//    initialisation or set_state) keeps the red populations in planes 27..53
-//    at the node itself ("unshifted") and is read that way by the first step.
-//  * A step: density pass (phi, rho - rho_b0, rho_r/rho per node), ghost fill
-//    of those fields, fused collide-perturb-recolour-stream kernel (reads 27
+//    float4 R = (x*, V) of every node, x* the fraction of the kept colour
+//    (the one of smaller reference density, see kept_sgn); readers rebuild
+//    f^* of direction i at x from d_i and R at the source node x - c_i, and
+//    the other colour as f - f^*.  A general state (after initialisation or
+//    set_state) keeps the kept colour's populations in planes 27..53 at the
+//    node itself ("unshifted") and is read that way by the first step.
+//  * A step: density pass (phi, rho - rho_b0, x* per node), ghost fill of
+//    those fields, fused collide-perturb-recolour-stream kernel (reads 27
 //    deviations and the (phi, rho) stencil, writes 27 deviations and R), ghost
 //    fill of the populations.  The jet outlet plane z = nz - 1 (convective
-//    condition) has its own density and collision kernels.
-//  * Launch geometry: grid (ceil(nx*ny/256), planes), z = blockIdx.y + z0.
+//    condition) is handled inside the density and fused kernels.
+//  * Launch geometry: the two stencil kernels take tiles of 128-node x-rows
+//    (see "stencil tiles"), z = blockIdx.y + z0; the other kernels a flat
+//    grid (ceil(nx*ny/256), planes).
 //  * Collision: with s0 = s1 = 0 and s2b = s3..s6 = 1 (Sec. II) the GMRT
 //    collision (Eq. scoll) leaves every central moment at its equilibrium
 //    value plus half the forcing moment, except the five deviatoric second-
@@ -114,7 +118,7 @@ struct KP {
     long long t;       // time level of the state that is read
     int unshifted;     // general state (54 planes) stored without the streaming shift
     const float* inlet_uz;
-    const float4* R;   // (rho_r/rho, V) of the post-collision state that is read
+    const float4* R;   // (tagged minority fraction, V) of the state that is read
     const uint4* Qrec; // referenced 16-bit storage: reference record of the state that is read
 };
 
@@ -283,70 +287,117 @@ __device__ __forceinline__ float inlet_feq_dir(const KP& k, int xg, int yg, long
     return k.rho_r0 * wgt(I) * (kap_r + poly);  // |c_I| >= 1 here: varphi_I = w_I kappa_r
 }
 
+// ---------------------------------------------------------------- colour fractions
+// The recolouring of a node needs x_r = rho_r/rho and x_b = 1 - x_r.  FP32
+// keeps a fraction near 1 only to an absolute 2^-24, which leaves the other
+// colour a relative error 2^-24/x, and Eq. order multiplies the error of
+// rho_k by rho/rho_k0 (up to gamma where the dense colour dominates).  A node
+// therefore keeps the fraction of its minority colour, with full relative
+// precision at both ends, and marks which colour that is in the lowest
+// mantissa bit: 0 red (the value is x_r), 1 blue (the value is x_b).  The
+// mark costs one bit of the fraction: the value is the FP32 number nearest to
+// the fraction among those with the right lowest bit (an unbiased rounding to
+// a grid of two ulps, so colour masses do not drift).  The other colour is
+// always formed as the colour-blind value minus the kept one.
+__device__ __forceinline__ uint32_t blue_kept(float s) { return __float_as_uint(s) & 1u; }
+__device__ __forceinline__ float frac_tag(double x, uint32_t blue)
+{
+    const float f = (float)x;
+    uint32_t b = __float_as_uint(f);
+    if ((b & 1u) != blue) {
+        if ((b & 0x7fffffffu) == 0u)
+            b |= 1u;  // +-0: the smallest magnitude that carries the mark
+        else
+            b += fabs(x) > fabs((double)f) ? 1u : 0xffffffffu;  // one ulp towards x (in magnitude)
+    }
+    return __uint_as_float(b);
+}
+// the fraction of colour `blue` (0 red, 1 blue) from a tagged value s
+__device__ __forceinline__ float frac_of(float s, uint32_t blue) { return blue_kept(s) == blue ? s : 1.f - s; }
+
 // ---------------------------------------------------------------- pull
 // Pre-collision value of direction I at padded node n of a post-collision
 // (shifted) state: d from plane I at n - c_I (an interior node or a filled
-// ghost cell), f^r rebuilt from R there.
-template <class S, int I, bool WANT_FR>
+// ghost cell), both colours rebuilt from R there (Eqs. op3r/op3b):
+//   f^k*_i = x_k f'_i +- (w_i/|c_i|) c_i . V   (+ red, - blue),
+// the kept colour from its fraction, the other as f - f^k (formed in FP64,
+// rounded once).
+__device__ __forceinline__ float other_colour(const KP& k, int i, float d, float fk)
+{
+    return (float)(((double)d + wgtd(i) * (double)k.rho_b0) - (double)fk);
+}
+
+template <class S, int I, bool WANT_F>
 __device__ __forceinline__ void pull_shifted(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
-                                             float& d, float& fr)
+                                             float& d, float& fr, float& fb)
 {
     const uint32_t s = n - (uint32_t)doff(k, kCX[I], kCY[I], kCZ[I]);
     d = load_dev<S, I>(src, k, s);
-    if (WANT_FR) {
+    if (WANT_F) {
         const float4 r = ldp(k.R, s);
-        float v = r.x * (d + wgt(I) * k.rho_b0);
-        if (I != 0) v += (wgt(I) * inv_len(I)) * (kCX[I] * r.y + kCY[I] * r.z + kCZ[I] * r.w);
-        fr = v;
+        const float f = d + wgt(I) * k.rho_b0;
+        const float vt = I == 0 ? 0.f : (wgt(I) * inv_len(I)) * (kCX[I] * r.y + kCY[I] * r.z + kCZ[I] * r.w);
+        const uint32_t bl = blue_kept(r.x);
+        const float fk = r.x * f + (bl ? -vt : vt);
+        const float fo = other_colour(k, I, d, fk);
+        fr = bl ? fo : fk;
+        fb = bl ? fk : fo;
     }
 }
 
-// value of direction I of a general state stored at node n itself
-template <class S, int I, bool WANT_FR>
+// value of direction I of a general state stored at node n itself: planes
+// Q..2Q-1 hold the populations of the colour the flag of R[n] names
+template <class S, int I, bool WANT_F>
 __device__ __forceinline__ void pull_general(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
-                                             float& d, float& fr)
+                                             float& d, float& fr, float& fb)
 {
     d = S::dec(ldp(src + (size_t)I * k.NP, n));
-    if (WANT_FR) fr = S::dec(ldp(src + (size_t)(Q + I) * k.NP, n));
+    if (WANT_F) {
+        const float fk = S::dec(ldp(src + (size_t)(Q + I) * k.NP, n));
+        const float fo = other_colour(k, I, d, fk);
+        const uint32_t bl = blue_kept(ldp(k.R, n).x);
+        fr = bl ? fo : fk;
+        fb = bl ? fk : fo;
+    }
 }
 
-template <class S, bool WANT_FR, bool SHIFTED, int I = 0>
+template <class S, bool WANT_F, bool SHIFTED, int I = 0>
 __device__ __forceinline__ void pull_dirs(const typename S::T* __restrict__ src, const KP& k, uint32_t n, float* d,
-                                          float* fr)
+                                          float* fr, float* fb)
 {
     if constexpr (I < Q) {
         if constexpr (SHIFTED)
-            pull_shifted<S, I, WANT_FR>(src, k, n, d[I], fr[I]);
+            pull_shifted<S, I, WANT_F>(src, k, n, d[I], fr[I], fb[I]);
         else
-            pull_general<S, I, WANT_FR>(src, k, n, d[I], fr[I]);
-        pull_dirs<S, WANT_FR, SHIFTED, I + 1>(src, k, n, d, fr);
+            pull_general<S, I, WANT_F>(src, k, n, d[I], fr[I], fb[I]);
+        pull_dirs<S, WANT_F, SHIFTED, I + 1>(src, k, n, d, fr, fb);
     }
 }
 
-// the 27 pre-collision values (and red populations) at padded node n
-template <class S, bool WANT_FR>
+// the 27 pre-collision deviations (and colour populations) at padded node n
+template <class S, bool WANT_F>
 __device__ __forceinline__ void pull_all(const typename S::T* __restrict__ src, const KP& k, uint32_t n, float* d,
-                                         float* fr)
+                                         float* fr, float* fb)
 {
     if (k.unshifted)
-        pull_dirs<S, WANT_FR, false>(src, k, n, d, fr);
+        pull_dirs<S, WANT_F, false>(src, k, n, d, fr, fb);
     else
-        pull_dirs<S, WANT_FR, true>(src, k, n, d, fr);
+        pull_dirs<S, WANT_F, true>(src, k, n, d, fr, fb);
 }
 
 // Pre-collision state of an outlet node (x, y, nz - 1) by the convective
 // condition f(N) = [f_prev(N) + lam f(N - 1)] / (1 + lam), lam = max(0, u_z(N - 1))
 // evaluated on the freshly streamed populations of the node below; hprev holds
-// the outlet plane of the previous step (d, then f^r).
+// the outlet plane of the previous step (d, then f^r); blue is formed as f - f^r.
 template <class S>
 __device__ void outlet_state(const typename S::T* __restrict__ src, const KP& k, const float* __restrict__ hprev,
-                             const Node& nd, float* d, float* fr)
+                             const Node& nd, float* d, float* fr, float* fb)
 {
     if (k.unshifted) {
-        pull_all<S, true>(src, k, nd.n, d, fr);
+        pull_all<S, true>(src, k, nd.n, d, fr, fb);
         return;
     }
-    pull_all<S, true>(src, k, nd.n - (uint32_t)(k.px * k.py), d, fr);
+    pull_all<S, true>(src, k, nd.n - (uint32_t)(k.px * k.py), d, fr, fb);
     float m0 = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -361,18 +412,20 @@ __device__ void outlet_state(const typename S::T* __restrict__ src, const KP& k,
     for (int i = 0; i < Q; ++i) {
         d[i] = (hprev[(size_t)i * k.plane + nd.q] + lam * d[i]) * inv;
         fr[i] = (hprev[(size_t)(Q + i) * k.plane + nd.q] + lam * fr[i]) * inv;
+        fb[i] = other_colour(k, i, d[i], fr[i]);
     }
 }
 
-// full pre-collision state (54 values) of any interior node
+// full pre-collision state (deviations and both colours) of any interior node
 template <int BC, class S>
 __device__ __forceinline__ void read_state(const typename S::T* __restrict__ src, const KP& k,
-                                           const float* __restrict__ hprev, const Node& nd, float* d, float* fr)
+                                           const float* __restrict__ hprev, const Node& nd, float* d, float* fr,
+                                           float* fb)
 {
     if (BC == LBM_BC_JET && nd.z == k.nz - 1)
-        outlet_state<S>(src, k, hprev, nd, d, fr);
+        outlet_state<S>(src, k, hprev, nd, d, fr, fb);
     else
-        pull_all<S, true>(src, k, nd.n, d, fr);
+        pull_all<S, true>(src, k, nd.n, d, fr, fb);
 }
 
 // ---------------------------------------------------------------- block reduction (FP64 audit)
@@ -466,7 +519,25 @@ __device__ __forceinline__ void load_window(T* __restrict__ win, const T* __rest
 }
 
 // ---------------------------------------------------------------- density pass
-// fields: PD = (phi, rho - rho_b0) per padded node, XR = rho_r / rho.
+// fields: PD = (phi, rho - rho_b0) per padded node and XR = the minority
+// colour's fraction, tagged (see "colour fractions"), from the mass sum
+// m0 = rho - rho_b0 and the two colour masses.
+__device__ __forceinline__ void store_pd(float2* __restrict__ PD, const KP& k, uint32_t n, double m0, double rr,
+                                         double rb)
+{
+    const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
+    stp(PD, n, make_float2((float)((a - b) / (a + b)), (float)m0));  // Eq. order
+}
+
+__device__ __forceinline__ void store_fields_sums(float2* __restrict__ PD, float* __restrict__ XR, const KP& k,
+                                                  uint32_t n, double m0, double rr, double rb)
+{
+    const double rho = (double)k.rho_b0 + m0;
+    store_pd(PD, k, n, m0, rr, rb);
+    const uint32_t bl = rr > rb;
+    stp(XR, n, frac_tag((bl ? rb : rr) / rho, bl));
+}
+
 __device__ __forceinline__ void store_fields(float2* __restrict__ PD, float* __restrict__ XR, const KP& k, uint32_t n,
                                              const float* d, const float* fr)
 {
@@ -476,11 +547,7 @@ __device__ __forceinline__ void store_fields(float2* __restrict__ PD, float* __r
         m0 += (double)d[i];
         rr += (double)fr[i];
     }
-    const double rho = (double)k.rho_b0 + m0;
-    const double rb = rho - rr;
-    const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
-    stp(PD, n, make_float2((float)((a - b) / (a + b)), (float)m0));  // Eq. order
-    stp(XR, n, (float)(rr / rho));
+    store_fields_sums(PD, XR, k, n, m0, rr, (double)k.rho_b0 + m0 - rr);
 }
 
 __host__ __device__ constexpr double inv_lend(int i)
@@ -488,64 +555,45 @@ __host__ __device__ constexpr double inv_lend(int i)
     return csq(i) == 1 ? 1.0 : csq(i) == 2 ? 0.70710678118654752440 : 0.57735026918962576451;
 }
 
-// Mass and red mass of the pre-collision state at n.  The mass sum m0 runs in
+// Mass and colour masses of a general state at n.  The mass sum m0 runs in
 // FP64 (an exact sum of the stored deviations: mass is conserved up to the
-// storage rounding).  The red mass of a shifted state is written as
-//   rho_r = xr(x) rho + sum_{i>=1} [(xr(x - c_i) - xr(x)) f_i + (w_i/|c_i|) c_i . V(x - c_i)],
-// an FP64 main term plus FP32 corrections that vanish wherever xr and V are
-// uniform (so pure phases carry no rounding bias).
-template <class S, bool SHIFTED, int I = 0>
-__device__ __forceinline__ void accum_density(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
-                                              double& m0, double& rr, float& xr0, float& corr)
+// storage rounding); mk is the mass of the colour the planes Q..2Q-1 hold.
+template <class S, int I = 0>
+__device__ __forceinline__ void accum_general(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
+                                              double& m0, double& mk)
 {
     if constexpr (I < Q) {
-        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
-        if constexpr (SHIFTED) {
-            const uint32_t s = n - (uint32_t)doff(k, cx, cy, cz);
-            const float d = load_dev<S, I>(src, k, s);
-            const float4 r = ldp(k.R, s);
-            m0 += (double)d;
-            if (I == 0) {
-                xr0 = r.x;
-            } else {
-                corr += (r.x - xr0) * (d + wgt(I) * k.rho_b0) +
-                        (wgt(I) * inv_len(I)) * (cx * r.y + cy * r.z + cz * r.w);
-            }
-        } else {
-            m0 += (double)S::dec(ldp(src + (size_t)I * k.NP, n));
-            rr += (double)S::dec(ldp(src + (size_t)(Q + I) * k.NP, n));
-        }
-        accum_density<S, SHIFTED, I + 1>(src, k, n, m0, rr, xr0, corr);
+        m0 += (double)S::dec(ldp(src + (size_t)I * k.NP, n));
+        mk += (double)S::dec(ldp(src + (size_t)(Q + I) * k.NP, n));
+        accum_general<S, I + 1>(src, k, n, m0, mk);
     }
 }
 
-__device__ __forceinline__ void store_fields_sums(float2* __restrict__ PD, float* __restrict__ XR, const KP& k,
-                                                  uint32_t n, double m0, double rr)
-{
-    const double rho = (double)k.rho_b0 + m0;
-    const double rb = rho - rr;
-    const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
-    stp(PD, n, make_float2((float)((a - b) / (a + b)), (float)m0));  // Eq. order
-    stp(XR, n, (float)(rr / rho));
-}
-
-// the shifted-state sums of accum_density from pulled deviations d and R read
-// from the LDS window
+// Mass and minority-colour mass of a shifted state at n, from the pulled
+// deviations d and the R of the source nodes in the LDS window.  The colour m
+// is the one node n kept in the previous step (its own R, direction 0); its
+// mass is written
+//   rho_m = x_m(x) rho + sum_{i>=1} [(x_m(x - c_i) - x_m(x)) f_i +- (w_i/|c_i|) c_i . V(x - c_i)],
+// an FP64 main term plus FP32 corrections (cf: fractions, cv: recolouring
+// vectors, + for red, - for blue) that vanish wherever x_m and V are uniform,
+// so pure phases carry no rounding bias.
 template <int I = 0>
 __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, const float4* __restrict__ win,
-                                                  int lx, int ly, double& m0, float& xr0, float& corr)
+                                                  int lx, int ly, double& m0, float& x0, uint32_t& bl, float& cf,
+                                                  float& cv)
 {
     if constexpr (I < Q) {
         constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
         const float4 r = win[wslot<DTY>(lx, ly, -cx, -cy, -cz)];
         m0 += (double)d[I];
         if (I == 0) {
-            xr0 = r.x;
+            x0 = r.x;
+            bl = blue_kept(r.x);
         } else {
-            corr += (r.x - xr0) * (d[I] + wgt(I) * k.rho_b0) +
-                    (wgt(I) * inv_len(I)) * (cx * r.y + cy * r.z + cz * r.w);
+            cf += (frac_of(r.x, bl) - x0) * (d[I] + wgt(I) * k.rho_b0);
+            cv += (wgt(I) * inv_len(I)) * (cx * r.y + cy * r.z + cz * r.w);
         }
-        accum_density_win<I + 1>(k, d, win, lx, ly, m0, xr0, corr);
+        accum_density_win<I + 1>(k, d, win, lx, ly, m0, x0, bl, cf, cv);
     }
 }
 
@@ -561,8 +609,8 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
     const Node& nd = t.nd;
     if (BC == LBM_BC_JET && t.z == k.nz - 1) {
         if (!nd.valid) return;
-        float d[Q], fr[Q];
-        outlet_state<S>(src, k, hprev, nd, d, fr);
+        float d[Q], fr[Q], fb[Q];
+        outlet_state<S>(src, k, hprev, nd, d, fr, fb);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             hcur[(size_t)i * k.plane + nd.q] = d[i];
@@ -571,23 +619,26 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
         store_fields(PD, XR, k, nd.n, d, fr);
         return;
     }
-    double m0 = 0.0, rr = 0.0;
+    double m0 = 0.0, mk = 0.0;
     if (k.unshifted) {
         if (!nd.valid) return;
-        float xr0 = 0.f, corr = 0.f;
-        accum_density<S, false>(src, k, nd.n, m0, rr, xr0, corr);
-        store_fields_sums(PD, XR, k, nd.n, m0, rr);
+        accum_general<S>(src, k, nd.n, m0, mk);
+        const double mo = (double)k.rho_b0 + m0 - mk;
+        const bool bl = blue_kept(ldp(k.R, nd.n).x);
+        store_fields_sums(PD, XR, k, nd.n, m0, bl ? mo : mk, bl ? mk : mo);
         return;
     }
     load_window<DTY>(win, k.R, k, t);
     __syncthreads();
     if (!nd.valid) return;
     float d[Q], unused[Q];
-    pull_dirs<S, false, true>(src, k, nd.n, d, unused);
-    float xr0 = 0.f, corr = 0.f;
-    accum_density_win(k, d, win, t.lx, t.ly, m0, xr0, corr);
-    rr = (double)xr0 * ((double)k.rho_b0 + m0) + (double)corr;
-    store_fields_sums(PD, XR, k, nd.n, m0, rr);
+    pull_dirs<S, false, true>(src, k, nd.n, d, unused, unused);
+    float x0 = 0.f, cf = 0.f, cv = 0.f;
+    uint32_t bl = 0;
+    accum_density_win(k, d, win, t.lx, t.ly, m0, x0, bl, cf, cv);
+    const double rho = (double)k.rho_b0 + m0;
+    mk = (double)x0 * rho + (double)(cf + (bl ? -cv : cv));
+    store_fields_sums(PD, XR, k, nd.n, m0, bl ? rho - mk : mk, bl ? mk : rho - mk);
 }
 
 
@@ -707,7 +758,7 @@ __global__ __launch_bounds__(BLOCK) void k_pop_ghosts(typename S::T* __restrict_
     const uint32_t wi = pidx(k, clampc(c.x, k.nx), clampc(c.y, k.ny), clampc(c.z, k.nz));
     ghost_dirs<BC, S>(dst, k, c, gi, wi, m, inlet);
     if (inlet) {
-        Rout[gi] = make_float4(1.f, 0.f, 0.f, 0.f);
+        Rout[gi] = make_float4(frac_tag(0.0, 1u), 0.f, 0.f, 0.f);  // pure red: x_b = 0
         if (S::kEqRef) Qout[gi] = make_uint4(0u, 0u, 0u, 0u);  // zero record: the stored value is the deviation
     } else {
         const float4 r = Rout[wi];
@@ -797,7 +848,7 @@ __device__ __forceinline__ void ghost_pop_x(const KP& k, const Node& nd, typenam
     }
 }
 
-// R = (rho_r/rho, V) of the x-wall ghost cell this node feeds: a copy
+// R = (x*, V) of the x-wall ghost cell this node feeds: a copy
 // (periodic) or with V_x reversed (free slip)
 template <int BC>
 __device__ __forceinline__ void ghost_R_x(const KP& k, const Node& nd, float4* __restrict__ Rout, float4 r, bool xl,
@@ -871,16 +922,16 @@ struct Basis1D {
 __device__ __forceinline__ constexpr float h2(int c) { return c == 0 ? -1.f : 0.5f; }
 
 // Collision, perturbation and recolouring of one node from its pre-collision
-// colour-blind deviations d, the centre values phic and xr = rho_r/rho and
-// the gradients; writes the 27 post-collision colour-blind deviations to dst
-// and (rho_r/rho, V) of the recolouring to Rout at node n.  FP64 only where a
+// colour-blind deviations d, the centre values phic and xk (the tagged
+// minority-colour fraction) and the gradients; writes the 27 post-collision
+// colour-blind deviations to dst and (xk, V) of the recolouring to Rout at n.  FP64 only where a
 // sum must be exact or an O(1) cancellation happens: the mass m0 and the
 // equilibrium offsets E0, E1 (zero in the pure phases).  The momentum and the
 // second moments are FP32 sums over opposite pairs (pair differences are exact
 // for nearly equal populations, so the momentum of a fluid at rest is exactly
 // zero).
 template <int BC, class S>
-__device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const float* d, float phic, float xr,
+__device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const float* d, float phic, float xk,
                                               const float (&g)[6], typename S::T* __restrict__ dst,
                                               float4* __restrict__ Rout, uint4* __restrict__ Qout)
 {
@@ -960,9 +1011,9 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
     const float gn = on ? sqrtf(G2) : 0.f;
     const float inv_gn = on ? 1.f / gn : 0.f;
     const float Agn = k.A * gn, Aign = k.A * inv_gn;
-    // recolouring vector V = beta (rho_r rho_b / rho) kappa n
-    const float rec = k.beta * xr * (1.f - xr) * rhof * (float)kap * inv_gn;
-    const float4 rv = make_float4(xr, rec * gpx, rec * gpy, rec * gpz);
+    // recolouring vector V = beta (rho_r rho_b / rho) kappa n (x_r x_b = xk (1 - xk))
+    const float rec = k.beta * xk * (1.f - xk) * rhof * (float)kap * inv_gn;
+    const float4 rv = make_float4(xk, rec * gpx, rec * gpy, rec * gpz);
     stp(Rout, n, rv);
     const float nub9 = 9.f * nubf;
     const bool xl = nd.x == 0, xh = nd.x == k.nx - 1;
@@ -1064,9 +1115,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
         for (int i = 0; i < Q; ++i) d[i] = hcur[(size_t)i * k.plane + nd.q];
     } else {
         float unused[Q];
-        pull_all<S, false>(src, k, nd.n, d, unused);
+        pull_all<S, false>(src, k, nd.n, d, unused, unused);
     }
-    const float xr = ldp(XR, nd.n);
+    const float xk = ldp(XR, nd.n);
     float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float phic;
     if constexpr (kWin) {
@@ -1076,7 +1127,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
         phic = ldp(PD, nd.n).x;
         gradients_f(PD, k, nd.n, g);
     }
-    collide_store<BC, S>(k, nd, d, phic, xr, g, dst, Rout, Qout);
+    collide_store<BC, S>(k, nd, d, phic, xk, g, dst, Rout, Qout);
 }
 
 
@@ -1085,7 +1136,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
 // + w_i [velocity terms of Eq. EES]} of the droplet / jet preset or of caller
 // fields (node order), evaluated in FP64 and rounded once to the storage format.
 template <class S>
-__global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst, KP k, int kind,
+__global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst, float4* __restrict__ Rw, KP k,
+                                                 int kind,
                                                  const float* __restrict__ frr, const float* __restrict__ frb,
                                                  const float* __restrict__ fu, double dcx, double dcy, double dcz,
                                                  double R, double W, double rho_r0, double rho_b0, double alpha_r,
@@ -1115,6 +1167,8 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst,
     }
     const double u2 = ux * ux + uy * uy + uz * uz;
     const double kap_r = 27.0 * (1.0 - alpha_r) / 19.0, kap_b = 27.0 * (1.0 - alpha_b) / 19.0;
+    const uint32_t bl = rr > rb;  // planes Q..2Q-1 keep the minority colour
+    stp(Rw, nd.n, make_float4(frac_tag(0.0, bl), 0.f, 0.f, 0.f));
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double w = wgtd(i);
@@ -1130,30 +1184,39 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename S::T* __restrict__ dst,
         }
         const double dv = (fv + fb) - w * rho_ref;  // deviation from the kernels' reference density
         stp(dst + (size_t)i * NP, nd.n, S::enc((float)dv));
-        stp(dst + (size_t)(Q + i) * NP, nd.n, S::enc((float)fv));
+        stp(dst + (size_t)(Q + i) * NP, nd.n, S::enc((float)(bl ? fb : fv)));
     }
 }
 
-// set an explicit (fr, fb) FP32 state (node order), general form; d is
-// formed in FP64 and rounded once
+// set an explicit (fr, fb) FP32 state (node order), general form: d formed in
+// FP64 and rounded once, and the populations of the node's minority colour
+// (flagged in Rw)
 template <class S>
-__global__ __launch_bounds__(BLOCK) void k_set_state(typename S::T* __restrict__ dst, KP k,
+__global__ __launch_bounds__(BLOCK) void k_set_state(typename S::T* __restrict__ dst, float4* __restrict__ Rw, KP k,
                                                       const float* __restrict__ st, double rho_b0)
 {
     const Node nd = this_node(k);
     if (!nd.valid) return;
     const size_t NP = k.NP, N = k.N;
     const uint32_t u_idx = (uint32_t)nd.z * k.plane + nd.q;
+    double rr = 0.0, rb = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rr += (double)st[(size_t)i * N + u_idx];
+        rb += (double)st[(size_t)(Q + i) * N + u_idx];
+    }
+    const uint32_t bl = rr > rb;
+    stp(Rw, nd.n, make_float4(frac_tag(0.0, bl), 0.f, 0.f, 0.f));
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float fr = st[(size_t)i * N + u_idx], fb = st[(size_t)(Q + i) * N + u_idx];
         const double dv = ((double)fr + (double)fb) - wgtd(i) * rho_b0;
         stp(dst + (size_t)i * NP, nd.n, S::enc((float)dv));
-        stp(dst + (size_t)(Q + i) * NP, nd.n, S::enc(fr));
+        stp(dst + (size_t)(Q + i) * NP, nd.n, S::enc(bl ? fb : fr));
     }
 }
 
-// current state as (fr, fb) FP32 in node order (blue formed in FP64, rounded once)
+// current state as (fr, fb) FP32 in node order
 template <int BC, class S>
 __global__ __launch_bounds__(BLOCK) void k_get_state(const typename S::T* __restrict__ src,
                                                       const float* __restrict__ hprev, KP k, float* __restrict__ st,
@@ -1163,12 +1226,12 @@ __global__ __launch_bounds__(BLOCK) void k_get_state(const typename S::T* __rest
     if (!nd.valid) return;
     const size_t N = k.N;
     const uint32_t u_idx = (uint32_t)nd.z * k.plane + nd.q;
-    float d[Q], fr[Q];
-    read_state<BC, S>(src, k, hprev, nd, d, fr);
+    float d[Q], fr[Q], fb[Q];
+    read_state<BC, S>(src, k, hprev, nd, d, fr, fb);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         st[(size_t)i * N + u_idx] = fr[i];
-        st[(size_t)(Q + i) * N + u_idx] = (float)(((double)d[i] + wgtd(i) * rho_b0) - (double)fr[i]);
+        st[(size_t)(Q + i) * N + u_idx] = fb[i];
     }
 }
 
@@ -1182,19 +1245,19 @@ __global__ __launch_bounds__(BLOCK) void k_macro(const typename S::T* __restrict
     const Node nd = this_node(k);
     double acc[5] = {0, 0, 0, 0, 0};
     if (nd.valid) {
-        float d[Q], fr[Q];
-        read_state<BC, S>(src, k, hprev, nd, d, fr);
-        double m0 = 0.0, rr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        float d[Q], fr[Q], fb[Q];
+        read_state<BC, S>(src, k, hprev, nd, d, fr, fb);
+        double m0 = 0.0, rr = 0.0, rb = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             m0 += (double)d[i];
             rr += (double)fr[i];
+            rb += (double)fb[i];
             if (kCX[i]) jx += kCX[i] * (double)d[i];
             if (kCY[i]) jy += kCY[i] * (double)d[i];
             if (kCZ[i]) jz += kCZ[i] * (double)d[i];
         }
         const double rho = (double)k.rho_b0 + m0;
-        const double rb = rho - rr;
         const double px = jx + 0.5 * m0 * k.gx, py = jy + 0.5 * m0 * k.gy, pz = jz + 0.5 * m0 * k.gz;
         const size_t n = (size_t)nd.z * k.plane + nd.q;
         if (o_rr) o_rr[n] = (float)rr;

@@ -2,8 +2,9 @@
 arithmetic) through the C ABI.
 
 * Codec: a state written with lbm_set_state is stored as the deviation d and
-  the red populations rounded to the storage format; lbm_get_state returns
-  them decoded.  Checked bit for bit against torch's round-to-nearest-even
+  the populations of each node's minority colour (by mass) rounded to the
+  storage format; lbm_get_state returns them decoded and forms the other
+  colour as (d + w rho_b0) - f^k.  Checked bit for bit against torch's round-to-nearest-even
   conversions (the library encodes with the gfx950 conversion instructions).
 * Error against the FP64 oracle, per field (rho, u, phi), for every storage
   form on a jet with the same boundaries, buoyancy and inlet noise as the
@@ -39,9 +40,15 @@ def test_codec_round_trip(torch, orc, storage):
     sim.close()
     tdt = torch.bfloat16 if storage.startswith("bf16") else torch.float16
     w = np.asarray(orc.lattice()[1], np.float64)  # lattice weights in the velocity-set order
-    # red populations: the stored value is the RNE conversion of the FP32 input
-    fr_ref = torch.from_numpy(st32[:Q]).to(tdt).float().numpy()
-    assert np.array_equal(got[:Q], fr_ref), "red populations differ from torch's RNE conversion"
+    # each node keeps its minority colour (red unless sum fr > sum fb); the
+    # stored value is the RNE conversion of the FP32 input
+    blue = st32[:Q].astype(np.float64).sum(0) > st32[Q:].astype(np.float64).sum(0)
+    assert 0 < blue.sum() < blue.size, "the random state should mix both cases"
+    fk_in = np.where(blue, st32[Q:], st32[:Q])
+    fk_got = np.where(blue, got[Q:], got[:Q])
+    fo_got = np.where(blue, got[:Q], got[Q:])
+    fk_ref = torch.from_numpy(np.ascontiguousarray(fk_in)).to(tdt).float().numpy()
+    assert np.array_equal(fk_got, fk_ref), "minority-colour populations differ from torch's RNE conversion"
     # deviation: d = fr + fb - w rho_b0 formed in FP64 and rounded to the storage
     # format: BF16 through FP32 (two roundings, as the kernel does), FP16 in one
     # correctly rounded step (the compiler converts FP64 to FP16 directly)
@@ -51,10 +58,10 @@ def test_codec_round_trip(torch, orc, storage):
     else:
         d_ref = d64.astype(np.float16).astype(np.float64)
     d_got = (got[:Q].astype(np.float64) + got[Q:].astype(np.float64)) - w[:, None] * prob.rho_b0
-    # get_state forms blue in FP64 and rounds it once to FP32
-    tol = 2.0 ** -24 * np.abs(got[Q:]).astype(np.float64) * 1.01
+    # get_state forms the other colour (d + w rho_b0) - f^k in FP64 and rounds it once
+    tol = 2.0 ** -24 * np.abs(fo_got).astype(np.float64) * 1.01
     assert np.all(np.abs(d_got - d_ref) <= tol), np.abs(d_got - d_ref).max()
-    say(f"{storage}: codec matches torch RNE on {st32[:Q].size} red values and deviations")
+    say(f"{storage}: codec matches torch RNE on {fk_in.size} minority-colour values and deviations")
 
 
 def test_storage_error_vs_oracle(torch, orc):
