@@ -318,8 +318,17 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
                 HIP_CHECK(hipEventRecord(e[0], h->stream));
             }
             // density pass (jet: the outlet plane by the convective condition)
-            hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR,
-                               hprev, hcur, k);
+            if (jet) {
+                const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1)), go(h->grid_dtiles.x, 1);
+                hipLaunchKernelGGL((k_density<S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k);
+                LAUNCH_CHECK();
+                KP ko = k;
+                ko.z0 = h->p.nz - 1;
+                hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, hprev,
+                                   hcur, ko);
+            } else {
+                hipLaunchKernelGGL((k_density<S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k);
+            }
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
             hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);

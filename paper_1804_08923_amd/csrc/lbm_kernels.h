@@ -597,28 +597,16 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
     }
 }
 
-// Jet: the blocks of the outlet plane (z = nz - 1) take its state from the
-// convective condition instead and record it in hcur for the collision.
-template <int BC, class S>
+// Density pass over the planes of the grid (for the jet all but the outlet
+// plane, which k_outlet_density takes: its branch would double this kernel's
+// register count and halve its occupancy).
+template <class S>
 __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
-                                                     float* __restrict__ XR, const float* __restrict__ hprev,
-                                                     float* __restrict__ hcur, KP k)
+                                                     float* __restrict__ XR, KP k)
 {
     __shared__ float4 win[TileShape<DTY>::W];
     const Tile t = this_tile<DTY>(k);
     const Node& nd = t.nd;
-    if (BC == LBM_BC_JET && t.z == k.nz - 1) {
-        if (!nd.valid) return;
-        float d[Q], fr[Q], fb[Q];
-        outlet_state<S>(src, k, hprev, nd, d, fr, fb);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            hcur[(size_t)i * k.plane + nd.q] = d[i];
-            hcur[(size_t)(Q + i) * k.plane + nd.q] = fr[i];
-        }
-        store_fields(PD, XR, k, nd.n, d, fr);
-        return;
-    }
     double m0 = 0.0, mk = 0.0;
     if (k.unshifted) {
         if (!nd.valid) return;
@@ -639,6 +627,27 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
     const double rho = (double)k.rho_b0 + m0;
     mk = (double)x0 * rho + (double)(cf + (bl ? -cv : cv));
     store_fields_sums(PD, XR, k, nd.n, m0, bl ? rho - mk : mk, bl ? mk : rho - mk);
+}
+
+// Jet outlet plane (z = nz - 1, launched with z0 = nz - 1 and one plane): its
+// state by the convective condition, recorded in hcur for the collision.
+template <class S>
+__global__ __launch_bounds__(DBLOCK) void k_outlet_density(const typename S::T* __restrict__ src,
+                                                            float2* __restrict__ PD, float* __restrict__ XR,
+                                                            const float* __restrict__ hprev, float* __restrict__ hcur,
+                                                            KP k)
+{
+    const Tile t = this_tile<DTY>(k);
+    const Node& nd = t.nd;
+    if (!nd.valid) return;
+    float d[Q], fr[Q], fb[Q];
+    outlet_state<S>(src, k, hprev, nd, d, fr, fb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        hcur[(size_t)i * k.plane + nd.q] = d[i];
+        hcur[(size_t)(Q + i) * k.plane + nd.q] = fr[i];
+    }
+    store_fields(PD, XR, k, nd.n, d, fr);
 }
 
 
@@ -1089,11 +1098,16 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
 
 
 // ---------------------------------------------------------------- fused collide-recolour-stream
-// three waves per SIMD: measured faster on MI355X than the four the register
-// count would allow (fewer concurrent streams contend for the caches).  Jet:
-// the outlet plane's pre-collision state is the one the density pass recorded.
+// waves per SIMD, measured on MI355X: four (at most 128 VGPRs) in FP32 and
+// the referenced forms, 7 % faster than three, where five spill; five for the
+// plain 16-bit forms (96 VGPRs, no spill), 1.4 % faster than four.  Jet: the
+// outlet plane's pre-collision state is the one the density pass recorded.
+template <class S>
+constexpr int kCollideWaves = (sizeof(typename S::T) == 2 && !S::kEqRef) ? 5 : 4;
+
 template <int BC, class S>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_collide(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kCollideWaves<S>, kCollideWaves<S>))) void
+k_collide(
     const typename S::T* __restrict__ src, typename S::T* __restrict__ dst, const float2* __restrict__ PD,
     const float* __restrict__ XR, const float* __restrict__ hcur, float4* __restrict__ Rout, uint4* __restrict__ Qout,
     KP k)

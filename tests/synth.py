@@ -43,6 +43,14 @@ def population_noise(n_nodes, seed, amp=1e-4):
     return amp * rng.standard_normal((2, 27, n_nodes))
 
 
+def population_noise_planes(n_nodes, seed, amp=1e-4):
+    """The values of population_noise, one (n_nodes,) plane at a time (red
+    planes 0..26, then blue), for lattices where the whole array is large."""
+    rng = np.random.default_rng(seed + 13)
+    for _ in range(2 * 27):
+        yield amp * rng.standard_normal(n_nodes)
+
+
 def random_state_fields(prob, seed):
     """(rho_r, rho_b, u) of a random but physical state of ``prob``'s lattice."""
     phi = smooth_phase(prob.nx, prob.ny, prob.nz, seed).ravel()

@@ -1,5 +1,6 @@
-"""Parity at full size: the 128x128x512 jet, FP32 storage, in the launch
-configuration bench.py times.
+"""Parity at full size: the 128x128x512 jet (the benchmark workload, in the
+launch configuration bench.py times) and the 256x256x1024 high-Re jet
+(67 M nodes), FP32 storage.
 
 One step from a random physical state of the whole lattice, taken over with
 lbm_set_state.  The oracle cannot step 8.4 M nodes in test time, so the
@@ -27,12 +28,13 @@ def torch():
     return t
 
 
-def test_full_size_jet_sampled_step(torch, orc):
-    from synth import population_noise, random_state_fields
+@pytest.mark.parametrize("workload", ["jet-128x128x512", "jet-256x256x1024"])
+def test_full_size_jet_sampled_step(torch, orc, workload):
+    from synth import population_noise_planes, random_state_fields
 
     from paper_1804_08923_amd.lbm import LBM
-    from paper_1804_08923_amd.workloads import jet_128
-    prob = jet_128()
+    from paper_1804_08923_amd.workloads import WORKLOADS
+    prob = WORKLOADS[workload]()
     nx, ny, nz = prob.nx, prob.ny, prob.nz
     N = prob.n_nodes
     say(f"full size {nx}x{ny}x{nz}: building a random state")
@@ -40,16 +42,16 @@ def test_full_size_jet_sampled_step(torch, orc):
     rr, rb, u = random_state_fields(prob, seed=101)
     fr, fb, _ = orc.init_fields(p, rr, rb, u)
     del rr, rb, u
-    nzs = population_noise(N, seed=101, amp=2e-4)
-    fr += np.where(fr > 1e-3, nzs[0], 0.0)
-    fb += np.where(fb > 1e-3, nzs[1], 0.0)
-    del nzs
-    st = np.concatenate([fr, fb]).astype(np.float32)
+    # the same noise as population_noise(N, 101, 2e-4), drawn plane by plane
+    st = np.empty((2 * Q, N), np.float32)
+    for j, (f, noise) in enumerate(zip([fr[i] for i in range(Q)] + [fb[i] for i in range(Q)],
+                                       population_noise_planes(N, seed=101, amp=2e-4))):
+        st[j] = f + np.where(f > 1e-3, noise, 0.0)
     del fr, fb
     fr64 = st[:Q].astype(np.float64)
     fb64 = st[Q:].astype(np.float64)
     t0 = 7
-    say("full size: one GPU step")
+    say(f"full size {nx}x{ny}x{nz}: one GPU step")
     sim = LBM(prob)
     sim.set_state(torch.from_numpy(st).cuda(), t=t0)
     sim.step(1)
@@ -58,7 +60,7 @@ def test_full_size_jet_sampled_step(torch, orc):
     del st
     torch.cuda.empty_cache()
 
-    say("full size: oracle fields and sampled node updates")
+    say(f"full size {nx}x{ny}x{nz}: oracle fields and sampled node updates")
     _, _, _, phi = orc.macroscopic(p, fr64, fb64)
     rho = fr64.sum(axis=0) + fb64.sum(axis=0)
     c, _ = orc.lattice()
@@ -78,8 +80,8 @@ def test_full_size_jet_sampled_step(torch, orc):
         return cache[s]
 
     rng = np.random.default_rng(5)
-    samples = [(2, 2, 2), (nx - 3, ny - 3, nz - 3), (127 - 2, 64, 256), (64, 2, 300), (2, ny - 3, 5),
-               (63, 1 + 2, 2), (64, 3, nz - 4)]
+    samples = [(2, 2, 2), (nx - 3, ny - 3, nz - 3), (nx - 3, ny // 2, nz // 2), (nx // 2, 2, nz // 2 + 44),
+               (2, ny - 3, 5), (nx // 2 - 1, 3, 2), (nx // 2, 3, nz - 4), (nx // 2 + 1, ny // 2, nz - 3)]
     samples += [tuple(int(v) for v in (rng.integers(2, nx - 2), rng.integers(2, ny - 2), rng.integers(2, nz - 3)))
                 for _ in range(60)]
     fmax = np.abs(out).max()
