@@ -179,6 +179,39 @@ __device__ __forceinline__ void stp(T* __restrict__ base, uint32_t idx, T v)
     *(T*)((char*)base + (idx * (uint32_t)sizeof(T))) = v;
 }
 
+// Population planes through buffer resources: the plane's base address sits
+// in scalar registers and the lane supplies only the byte offset n * sizeof(T)
+// (one offset shared by all 27 directions), so a pull costs no per-lane
+// address arithmetic.  The resource starts at element -off of the plane (the
+// shift of a pull direction) and its record count bounds every access to the
+// plane (out-of-range loads read 0 and out-of-range stores are dropped).
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* base, uint32_t elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)(elems * (uint32_t)sizeof(T)),
+                                             0x00020000);
+}
+// element n - off of plane p
+template <class T>
+__device__ __forceinline__ T ldpl(const T* __restrict__ p, int off, uint32_t NP, uint32_t n)
+{
+    const auto r = plane_rsrc(p - off, NP + (uint32_t)(off < 0 ? -off : off));
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, n * 4u, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, n * 2u, 0, 0));
+}
+// store v as element n of plane p
+template <class T>
+__device__ __forceinline__ void stpl(T* __restrict__ p, uint32_t NP, uint32_t n, T v)
+{
+    const auto r = plane_rsrc(p, NP);
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, n * 4u, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, n * 2u, 0, 0);
+}
+
 // ---------------------------------------------------------------- 16-bit storage
 // In the plain 16-bit forms the stored deviation d_i = f_i - w_i rho_b0 of a
 // moving direction carries the velocity part of the equilibrium,
@@ -231,22 +264,22 @@ __device__ __forceinline__ uint4 mirror_ref(uint4 q, int m)
     return q;
 }
 
-// deviation d_I = f_I - w_I rho_b0 of direction I stored at padded node s of a
-// post-collision (shifted) state
+// deviation d_I = f_I - w_I rho_b0 of direction I stored at padded node
+// s = n - off of a post-collision (shifted) state
 template <class S, int I>
-__device__ __forceinline__ float load_dev(const typename S::T* __restrict__ src, const KP& k, uint32_t s)
+__device__ __forceinline__ float load_dev(const typename S::T* __restrict__ src, const KP& k, uint32_t n, int off)
 {
     if constexpr (!S::kEqRef) {
-        return S::dec(ldp(src + (size_t)I * k.NP, s));
+        return S::dec(ldpl(src + (size_t)I * k.NP, off, k.NP, n));
     } else if constexpr (I == 0) {
-        const uint32_t hi = __builtin_bit_cast(uint16_t, ldp(src, s));
-        const uint32_t lo = __builtin_bit_cast(uint16_t, ldp(src + (size_t)Q * k.NP, s));
+        const uint32_t hi = __builtin_bit_cast(uint16_t, ldpl(src, off, k.NP, n));
+        const uint32_t lo = __builtin_bit_cast(uint16_t, ldpl(src + (size_t)Q * k.NP, off, k.NP, n));
         return __uint_as_float((hi << 16) | lo);
     } else {
-        const RefRec r = dec_ref<S>(ldp(k.Qrec, s));
+        const RefRec r = dec_ref<S>(ldp(k.Qrec, n - (uint32_t)off));
         const float cu = kCX[I] * r.ux + kCY[I] * r.uy + kCZ[I] * r.uz;
         const float u2 = r.ux * r.ux + r.uy * r.uy + r.uz * r.uz;
-        return S::dec(ldp(src + (size_t)I * k.NP, s)) + wgt(I) * (r.e + r.rho * eq_poly(cu, u2));
+        return S::dec(ldpl(src + (size_t)I * k.NP, off, k.NP, n)) + wgt(I) * (r.e + r.rho * eq_poly(cu, u2));
     }
 }
 
@@ -331,8 +364,9 @@ template <class S, int I, bool WANT_F>
 __device__ __forceinline__ void pull_shifted(const typename S::T* __restrict__ src, const KP& k, uint32_t n,
                                              float& d, float& fr, float& fb)
 {
-    const uint32_t s = n - (uint32_t)doff(k, kCX[I], kCY[I], kCZ[I]);
-    d = load_dev<S, I>(src, k, s);
+    const int off = doff(k, kCX[I], kCY[I], kCZ[I]);
+    const uint32_t s = n - (uint32_t)off;
+    d = load_dev<S, I>(src, k, n, off);
     if (WANT_F) {
         const float4 r = ldp(k.R, s);
         const float f = d + wgt(I) * k.rho_b0;
@@ -963,11 +997,13 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
     }
     const float m0 = (float)m0d;
     const float rhof = (float)((double)k.rho_b0 + m0d);
-    const float inv_rho = 1.f / rhof;
+    // hardware reciprocals (1 ulp): the node quantities need no correctly
+    // rounded division, and each IEEE division costs about ten instructions
+    const float inv_rho = __builtin_amdgcn_rcpf(rhof);
     // interpolated properties (Sec. II): alpha_bar, harmonic nu_bar, s2nu
     const float hpf = 0.5f * (1.f + phic), hmf = 0.5f * (1.f - phic);
-    const float nubf = 1.f / (hpf * k.inv_nu_r + hmf * k.inv_nu_b);
-    const float s2 = 1.f / (3.f * nubf + 0.5f);
+    const float nubf = __builtin_amdgcn_rcpf(hpf * k.inv_nu_r + hmf * k.inv_nu_b);
+    const float s2 = __builtin_amdgcn_rcpf(3.f * nubf + 0.5f);
     const double hp = 0.5 * (1.0 + (double)phic);
     const double abar = (double)k.alpha_b + hp * (double)k.dalpha;
     const double kap = (27.0 / 19.0) * (1.0 - abar);
@@ -1017,8 +1053,8 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
     // perturbation (squared projection, prefactor A) and recolouring weights
     const float G2 = gpx * gpx + gpy * gpy + gpz * gpz;
     const bool on = G2 > k.eps2;
-    const float gn = on ? sqrtf(G2) : 0.f;
-    const float inv_gn = on ? 1.f / gn : 0.f;
+    const float inv_gn = on ? __builtin_amdgcn_rsqf(G2) : 0.f;
+    const float gn = G2 * inv_gn;
     const float Agn = k.A * gn, Aign = k.A * inv_gn;
     // recolouring vector V = beta (rho_r rho_b / rho) kappa n (x_r x_b = xk (1 - xk))
     const float rec = k.beta * xk * (1.f - xk) * rhof * (float)kap * inv_gn;
@@ -1053,13 +1089,22 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
         const float dd = de + 0.5f * Fp + delta + pert;
         if constexpr (S::kEqRef) {
             const uint32_t b = __float_as_uint(dd);
-            stp(dst, n, __builtin_bit_cast(typename S::T, (uint16_t)(b >> 16)));
-            stp(dst + (size_t)Q * N, n, __builtin_bit_cast(typename S::T, (uint16_t)(b & 0xffffu)));
+            stpl(dst, k.NP, n, __builtin_bit_cast(typename S::T, (uint16_t)(b >> 16)));
+            stpl(dst + (size_t)Q * N, k.NP, n, __builtin_bit_cast(typename S::T, (uint16_t)(b & 0xffffu)));
         } else {
-            stp(dst, n, S::enc(dd));
+            stpl(dst, k.NP, n, S::enc(dd));
         }
     }
-    // opposite pairs (i, i + 1): shared even parts, odd parts change sign
+    // opposite pairs (i, i + 1): shared even parts, odd parts change sign.
+    // Per direction (w_i factored out; cu = c.u, cr = c.grad rho, cF = c.F,
+    // cg = c.grad phi):
+    //   even = f^(e) even part + F'/2 even part + perturbation
+    //        = K0 + cu (4.5 rho cu + 9 nu cr + 4.5 cF) + A/|g| cg^2,
+    //          K0 = E1 - 1.5 rho u^2 - 1.5 u.F - A |g|,
+    //   odd  = cu (K1 + 4.5 rho cu^2) + 1.5 cF,  K1 = rho (3 - 4.5 u^2)
+    const float K0 = E1f - 1.5f * rhof * u2 - 1.5f * uF - Agn;
+    const float K1 = rhof * (3.f - 4.5f * u2);
+    const float r45 = 4.5f * rhof;
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
         const int cx = kCX[i], cy = kCY[i], cz = kCZ[i];
@@ -1068,13 +1113,9 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
         const float cr = cx * grxf + cy * gryf + cz * grzf;
         const float cF = cx * Fxf + cy * Fyf + cz * Fzf;
         const float cg = cx * gpx + cy * gpy + cz * gpz;
-        const float de_e = w * (E1f + rhof * (4.5f * cu * cu - 1.5f * u2) + nub9 * cu * cr);
-        const float de_o = w * rhof * cu * (3.f + 4.5f * cu * cu - 4.5f * u2);
-        const float fp_e = 0.5f * w * (9.f * cu * cF - 3.f * uF);
-        const float fp_o = 1.5f * w * cF;
-        const float pert = w * (Aign * cg * cg - Agn);
-        const float even = de_e + fp_e + pert;
-        const float odd = de_o + fp_o;
+        const float t = r45 * cu + (nub9 * cr + 4.5f * cF);
+        const float even = w * (K0 + cu * t + (Aign * cg) * cg);
+        const float odd = w * (cu * (K1 + r45 * (cu * cu)) + 1.5f * cF);
         // direction i (+c) and i + 1 (-c)
         const float dl_p = U0[cy + 1][cz + 1] * bx.h0[cx + 1] + U1[cy + 1][cz + 1] * bx.h1[cx + 1]
                            + U2[cy + 1][cz + 1] * h2(cx);
@@ -1090,20 +1131,20 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
             dp -= re + ro;
             dm -= re - ro;
         }
-        stp(dst + (size_t)i * N, n, S::enc(dp));
-        stp(dst + (size_t)(i + 1) * N, n, S::enc(dm));
+        stpl(dst + (size_t)i * N, k.NP, n, S::enc(dp));
+        stpl(dst + (size_t)(i + 1) * N, k.NP, n, S::enc(dm));
         ghost_pair<BC, S>(i, k, nd, dst, dp, dm, xl, xh, yz_edge);
     }
 }
 
 
 // ---------------------------------------------------------------- fused collide-recolour-stream
-// waves per SIMD, measured on MI355X: four (at most 128 VGPRs) in FP32 and
-// the referenced forms, 7 % faster than three, where five spill; five for the
-// plain 16-bit forms (96 VGPRs, no spill), 1.4 % faster than four.  Jet: the
+// waves per SIMD, measured on MI355X: four (at most 128 VGPRs) in FP32, FP16
+// and the referenced forms, 7 % faster than three in FP32 (five spill there);
+// five for plain BF16 (96 VGPRs, no spill), 1.4 % faster than four.  Jet: the
 // outlet plane's pre-collision state is the one the density pass recorded.
 template <class S>
-constexpr int kCollideWaves = (sizeof(typename S::T) == 2 && !S::kEqRef) ? 5 : 4;
+constexpr int kCollideWaves = (__is_same(typename S::T, uint16_t) && !S::kEqRef) ? 5 : 4;
 
 template <int BC, class S>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kCollideWaves<S>, kCollideWaves<S>))) void
