@@ -752,29 +752,58 @@ __global__ __launch_bounds__(BLOCK) void k_field_ghosts(float2* __restrict__ PD,
 // specular reflection, the populations of the clamped node with the outside
 // components of c_I reversed and V mirrored alike; inside the inlet circle at
 // z = -1 the red inlet equilibrium (d = f^e - w rho_b0, R = (1, 0, 0, 0)).
+// Populations of ghost cell c (index gi) that a pull reads (directions
+// pointing into the lattice) from interior node wi: periodic copies, mirrored
+// copies (free slip; m = the reflected axes) or inlet equilibria.  All loads
+// are issued before the first store (the compiler cannot reorder loads past
+// stores to the same array).
+template <int BC, class S, int I>
+__device__ __forceinline__ bool ghost_in(const KP& k, const Ghost& c)
+{
+    constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
+    return (c.x >= 0 && c.x < k.nx ? true : (c.x < 0 ? cx > 0 : cx < 0)) &&
+           (c.y >= 0 && c.y < k.ny ? true : (c.y < 0 ? cy > 0 : cy < 0)) &&
+           (c.z >= 0 && c.z < k.nz ? true : (c.z < 0 ? cz > 0 : cz < 0));
+}
+
 template <int BC, class S, int I = 0>
+__device__ __forceinline__ void ghost_gather(const typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
+                                             uint32_t wi, int m, bool inlet, typename S::T* v)
+{
+    if constexpr (I < Q) {
+        constexpr int cz = kCZ[I];
+        if (ghost_in<BC, S, I>(k, c)) {
+            if (BC == LBM_BC_PERIODIC) {
+                v[I] = dst[(size_t)I * k.NP + wi];
+            } else if (cz > 0 && inlet) {
+                const float fe = inlet_feq_dir<(cz > 0 ? I : 5)>(k, c.x, c.y, k.t);
+                v[I] = S::enc(fe - wgt(I) * k.rho_b0);
+            } else {
+                const int J = kMirror.v[I * 8 + m];
+                v[I] = dst[(size_t)J * k.NP + wi];
+            }
+        }
+        ghost_gather<BC, S, I + 1>(dst, k, c, wi, m, inlet, v);
+    }
+}
+
+template <int BC, class S, int I = 0>
+__device__ __forceinline__ void ghost_scatter(typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
+                                              uint32_t gi, const typename S::T* v)
+{
+    if constexpr (I < Q) {
+        if (ghost_in<BC, S, I>(k, c)) dst[(size_t)I * k.NP + gi] = v[I];
+        ghost_scatter<BC, S, I + 1>(dst, k, c, gi, v);
+    }
+}
+
+template <int BC, class S>
 __device__ __forceinline__ void ghost_dirs(typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
                                            uint32_t gi, uint32_t wi, int m, bool inlet)
 {
-    if constexpr (I < Q) {
-        const size_t NP = k.NP;
-        constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
-        const bool in = (c.x >= 0 && c.x < k.nx ? true : (c.x < 0 ? cx > 0 : cx < 0)) &&
-                        (c.y >= 0 && c.y < k.ny ? true : (c.y < 0 ? cy > 0 : cy < 0)) &&
-                        (c.z >= 0 && c.z < k.nz ? true : (c.z < 0 ? cz > 0 : cz < 0));
-        if (in) {
-            if (BC == LBM_BC_PERIODIC) {
-                dst[(size_t)I * NP + gi] = dst[(size_t)I * NP + wi];
-            } else if (cz > 0 && inlet) {
-                const float fe = inlet_feq_dir<(cz > 0 ? I : 5)>(k, c.x, c.y, k.t);
-                dst[(size_t)I * NP + gi] = S::enc(fe - wgt(I) * k.rho_b0);
-            } else {
-                const int J = kMirror.v[I * 8 + m];
-                dst[(size_t)I * NP + gi] = dst[(size_t)J * NP + wi];
-            }
-        }
-        ghost_dirs<BC, S, I + 1>(dst, k, c, gi, wi, m, inlet);
-    }
+    typename S::T v[Q];
+    ghost_gather<BC, S>(dst, k, c, wi, m, inlet, v);
+    ghost_scatter<BC, S>(dst, k, c, gi, v);
 }
 
 template <int BC, class S>
