@@ -77,6 +77,41 @@ def test_single_step_random_state(torch, orc, shape):
         assert e < 1e-5, k
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 6, 4), (5, 1, 3), (3, 4, 1), (129, 2, 2)])
+def test_degenerate_periodic_lattices(torch, orc, shape):
+    """Lattices one node thick along some axis (a node is then its own
+    neighbour across the periodic wrap, and both ghost faces of that axis copy
+    the same node), and a row one node wider than a 128-node tile: 10 steps
+    from a random state against the oracle, populations of both colours."""
+    prob = _periodic_random_problem(*shape)
+    say(f"degenerate lattice {shape}")
+    p, fr, fb, h = random_state(orc, prob, seed=3 + sum(shape))
+    st, fr64, fb64 = state_to_f32(fr, fb)
+    sim = _sim(prob)
+    sim.set_state(torch.from_numpy(st).cuda(), t=0)
+    sim.step(10)
+    gr, gb = _gpu_state(sim)
+    sim.close()
+    orc.step(p, prob.A, fr64, fb64, np.zeros((2 * Q, p.nx * p.ny)), 0, 10)
+    scale = np.abs(fr64 + fb64).max()
+    err = max(np.abs(gr - fr64).max(), np.abs(gb - fb64).max()) / scale
+    say(f"  max pop err {err:.2e}")
+    assert err < 1e-5
+
+
+def test_zero_steps_is_a_no_op(torch, orc):
+    prob = _periodic_random_problem(8, 6, 4)
+    _, fr, fb, _ = random_state(orc, prob, seed=9)
+    st, _, _ = state_to_f32(fr, fb)
+    sim = _sim(prob)
+    sim.set_state(torch.from_numpy(st).cuda(), t=5)
+    before = sim.get_state().cpu().numpy()
+    sim.step(0)
+    assert sim.time == 5
+    assert np.array_equal(sim.get_state().cpu().numpy(), before)
+    sim.close()
+
+
 def _internal_state(sim, prob):
     """The GPU's stored state right after set_state (general form at each node of the
     padded lattice): d_i = f_i - w_i rho_b0 and the populations f^k_i of the node's
