@@ -235,3 +235,24 @@ def test_small_jet(torch, orc, steps):
     scale = np.abs(fr + fb).max()
     assert np.abs(gr - fr).max() / scale < 1e-5
     assert np.abs(gb - fb).max() / scale < 1e-5
+
+
+@pytest.mark.parametrize("shape,D", [((3, 3, 3), 2.0), ((130, 5, 4), 3.0)])
+def test_tiny_jets(torch, orc, shape, D):
+    """The jet boundaries where almost every node is next to a wall, the inlet
+    or the outlet (the 3x3x3 minimum), and on a row two nodes wider than a
+    128-node tile: 30 steps against the oracle."""
+    from paper_1804_08923_amd.workloads import jet_problem
+    prob = jet_problem("jet-tiny", *shape, D=D, u=0.04, gamma=2.0, eta=1.0, Re=20.0, We=10.0, Fr=2.0,
+                       steps=30, noise_amp=0.01, noise_seed=5)
+    say(f"tiny jet {shape} D={D}")
+    sim = _sim(prob)
+    sim.step(prob.steps)
+    gr, gb = _gpu_state(sim)
+    sim.close()
+    p, fr, fb, h = oracle_init(orc, prob)
+    orc.step(p, prob.A, fr, fb, h, 0, prob.steps)
+    scale = np.abs(fr + fb).max()
+    err = max(np.abs(gr - fr).max(), np.abs(gb - fb).max()) / scale
+    say(f"  max pop err {err:.2e}")
+    assert err < 1e-5
