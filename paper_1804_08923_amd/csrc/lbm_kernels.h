@@ -49,6 +49,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <type_traits>
 #include <stdlib.h>
 #include <string.h>
 
@@ -196,10 +197,15 @@ template <class T>
 __device__ __forceinline__ T ldpl(const T* __restrict__ p, int off, uint32_t NP, uint32_t n)
 {
     const auto r = plane_rsrc(p - off, NP + (uint32_t)(off < 0 ? -off : off));
-    if constexpr (sizeof(T) == 4)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, n * 4u, 0, 0));
+    const uint32_t b = n * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 16)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, b, 0, 0));
+    else if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, b, 0, 0));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, b, 0, 0));
     else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, n * 2u, 0, 0));
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, b, 0, 0));
 }
 // store v as element n of plane p
 template <class T>
@@ -276,7 +282,7 @@ __device__ __forceinline__ float load_dev(const typename S::T* __restrict__ src,
         const uint32_t lo = __builtin_bit_cast(uint16_t, ldpl(src + (size_t)Q * k.NP, off, k.NP, n));
         return __uint_as_float((hi << 16) | lo);
     } else {
-        const RefRec r = dec_ref<S>(ldp(k.Qrec, n - (uint32_t)off));
+        const RefRec r = dec_ref<S>(ldpl(k.Qrec, off, k.NP, n));
         const float cu = kCX[I] * r.ux + kCY[I] * r.uy + kCZ[I] * r.uz;
         const float u2 = r.ux * r.ux + r.uy * r.uy + r.uz * r.uz;
         return S::dec(ldpl(src + (size_t)I * k.NP, off, k.NP, n)) + wgt(I) * (r.e + r.rho * eq_poly(cu, u2));
@@ -611,15 +617,15 @@ __device__ __forceinline__ void accum_general(const typename S::T* __restrict__ 
 // an FP64 main term plus FP32 corrections (cf: fractions, cv: recolouring
 // vectors, + for red, - for blue) that vanish wherever x_m and V are uniform,
 // so pure phases carry no rounding bias.
-template <int I = 0>
+template <class M, int I = 0>
 __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, const float4* __restrict__ win,
-                                                  int lx, int ly, double& m0, float& x0, uint32_t& bl, float& cf,
+                                                  int lx, int ly, M& m0, float& x0, uint32_t& bl, float& cf,
                                                   float& cv)
 {
     if constexpr (I < Q) {
         constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
         const float4 r = win[wslot<DTY>(lx, ly, -cx, -cy, -cz)];
-        m0 += (double)d[I];
+        m0 += (M)d[I];
         if (I == 0) {
             x0 = r.x;
             bl = blue_kept(r.x);
@@ -627,7 +633,7 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
             cf += (frac_of(r.x, bl) - x0) * (d[I] + wgt(I) * k.rho_b0);
             cv += (wgt(I) * inv_len(I)) * (cx * r.y + cy * r.z + cz * r.w);
         }
-        accum_density_win<I + 1>(k, d, win, lx, ly, m0, x0, bl, cf, cv);
+        accum_density_win<M, I + 1>(k, d, win, lx, ly, m0, x0, bl, cf, cv);
     }
 }
 
@@ -657,7 +663,13 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
     pull_dirs<S, false, true>(src, k, nd.n, d, unused, unused);
     float x0 = 0.f, cf = 0.f, cv = 0.f;
     uint32_t bl = 0;
-    accum_density_win(k, d, win, t.lx, t.ly, m0, x0, bl, cf, cv);
+    // mass: exact FP64 sum of FP32 deviations; with 16-bit storage an FP32 sum
+    // (its rounding is far below the storage rounding, and it is exact in the
+    // pure phases, where the deviations vanish)
+    using MassT = typename std::conditional<sizeof(typename S::T) == 4, double, float>::type;
+    MassT ms = 0;
+    accum_density_win(k, d, win, t.lx, t.ly, ms, x0, bl, cf, cv);
+    m0 = (double)ms;
     const double rho = (double)k.rho_b0 + m0;
     mk = (double)x0 * rho + (double)(cf + (bl ? -cv : cv));
     store_fields_sums(PD, XR, k, nd.n, m0, bl ? rho - mk : mk, bl ? mk : rho - mk);
@@ -1010,12 +1022,12 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
     const size_t N = k.NP;
     const uint32_t n = nd.n;
     // raw moments of d up to second order
-    double m0d = (double)d[0];
+    double m0s = (double)d[0];
     float jx = 0.f, jy = 0.f, jz = 0.f;
     float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
-        m0d += (double)d[i] + (double)d[i + 1];
+        m0s += (double)d[i] + (double)d[i + 1];
         const float sp = d[i] + d[i + 1], df = d[i] - d[i + 1];
         if (kCX[i]) { jx += kCX[i] * df; pxx += sp; }
         if (kCY[i]) { jy += kCY[i] * df; pyy += sp; }
@@ -1024,6 +1036,7 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
         if (kCX[i] * kCZ[i]) pxz += (kCX[i] * kCZ[i]) * sp;
         if (kCY[i] * kCZ[i]) pyz += (kCY[i] * kCZ[i]) * sp;
     }
+    const double m0d = m0s;
     const float m0 = (float)m0d;
     const float rhof = (float)((double)k.rho_b0 + m0d);
     // hardware reciprocals (1 ulp): the node quantities need no correctly
