@@ -763,59 +763,80 @@ __global__ __launch_bounds__(BLOCK) void k_field_ghosts(float2* __restrict__ PD,
 // axis on which g lies outside.  Periodic: copy of the wrapped node.  Jet:
 // specular reflection, the populations of the clamped node with the outside
 // components of c_I reversed and V mirrored alike; inside the inlet circle at
-// z = -1 the red inlet equilibrium (d = f^e - w rho_b0, R = (1, 0, 0, 0)).
-// Populations of ghost cell c (index gi) that a pull reads (directions
-// pointing into the lattice) from interior node wi: periodic copies, mirrored
-// copies (free slip; m = the reflected axes) or inlet equilibria.  All loads
-// are issued before the first store (the compiler cannot reorder loads past
-// stores to the same array).
-template <int BC, class S, int I>
-__device__ __forceinline__ bool ghost_in(const KP& k, const Ghost& c)
+// z = -1 the red inlet equilibrium (d = f^e - w rho_b0, pure red R).
+//
+// The side of the cell on each axis (0 inside, 1 below, 2 above) selects one of
+// 26 compile-time variants, so the directions a cell feeds and their mirror
+// images are constants; all loads are issued before the first store (the
+// compiler cannot reorder loads past stores to the same array).
+template <int SX, int SY, int SZ, int I>
+__host__ __device__ constexpr bool ghost_feeds()
 {
-    constexpr int cx = kCX[I], cy = kCY[I], cz = kCZ[I];
-    return (c.x >= 0 && c.x < k.nx ? true : (c.x < 0 ? cx > 0 : cx < 0)) &&
-           (c.y >= 0 && c.y < k.ny ? true : (c.y < 0 ? cy > 0 : cy < 0)) &&
-           (c.z >= 0 && c.z < k.nz ? true : (c.z < 0 ? cz > 0 : cz < 0));
+    return (SX == 0 || (SX == 1 ? kCX[I] > 0 : kCX[I] < 0)) && (SY == 0 || (SY == 1 ? kCY[I] > 0 : kCY[I] < 0)) &&
+           (SZ == 0 || (SZ == 1 ? kCZ[I] > 0 : kCZ[I] < 0));
 }
 
-template <int BC, class S, int I = 0>
+template <int BC, class S, int SX, int SY, int SZ, int I = 0>
 __device__ __forceinline__ void ghost_gather(const typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
-                                             uint32_t wi, int m, bool inlet, typename S::T* v)
+                                             uint32_t wi, bool inlet, typename S::T* v)
 {
     if constexpr (I < Q) {
-        constexpr int cz = kCZ[I];
-        if (ghost_in<BC, S, I>(k, c)) {
-            if (BC == LBM_BC_PERIODIC) {
-                v[I] = dst[(size_t)I * k.NP + wi];
-            } else if (cz > 0 && inlet) {
-                const float fe = inlet_feq_dir<(cz > 0 ? I : 5)>(k, c.x, c.y, k.t);
-                v[I] = S::enc(fe - wgt(I) * k.rho_b0);
+        if constexpr (ghost_feeds<SX, SY, SZ, I>()) {
+            constexpr int m = (SX ? 1 : 0) | (SY ? 2 : 0) | (SZ ? 4 : 0);
+            constexpr int J = BC == LBM_BC_PERIODIC ? I : mirror_dir(I, m);
+            if constexpr (BC == LBM_BC_JET && SZ == 1 && SX == 0 && SY == 0) {
+                if (inlet) {
+                    v[I] = S::enc(inlet_feq_dir<I>(k, c.x, c.y, k.t) - wgt(I) * k.rho_b0);
+                } else {
+                    v[I] = ldp(dst + (size_t)J * k.NP, wi);
+                }
             } else {
-                const int J = kMirror.v[I * 8 + m];
-                v[I] = dst[(size_t)J * k.NP + wi];
+                v[I] = ldp(dst + (size_t)J * k.NP, wi);
             }
         }
-        ghost_gather<BC, S, I + 1>(dst, k, c, wi, m, inlet, v);
+        ghost_gather<BC, S, SX, SY, SZ, I + 1>(dst, k, c, wi, inlet, v);
     }
 }
 
-template <int BC, class S, int I = 0>
-__device__ __forceinline__ void ghost_scatter(typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
-                                              uint32_t gi, const typename S::T* v)
+template <class S, int SX, int SY, int SZ, int I = 0>
+__device__ __forceinline__ void ghost_scatter(typename S::T* __restrict__ dst, const KP& k, uint32_t gi,
+                                              const typename S::T* v)
 {
     if constexpr (I < Q) {
-        if (ghost_in<BC, S, I>(k, c)) dst[(size_t)I * k.NP + gi] = v[I];
-        ghost_scatter<BC, S, I + 1>(dst, k, c, gi, v);
+        if constexpr (ghost_feeds<SX, SY, SZ, I>()) stp(dst + (size_t)I * k.NP, gi, v[I]);
+        ghost_scatter<S, SX, SY, SZ, I + 1>(dst, k, gi, v);
     }
+}
+
+template <int BC, class S, int SX, int SY, int SZ>
+__device__ __forceinline__ void ghost_fill(typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
+                                          uint32_t gi, uint32_t wi, bool inlet)
+{
+    typename S::T v[Q];
+    ghost_gather<BC, S, SX, SY, SZ>(dst, k, c, wi, inlet, v);
+    ghost_scatter<S, SX, SY, SZ>(dst, k, gi, v);
 }
 
 template <int BC, class S>
 __device__ __forceinline__ void ghost_dirs(typename S::T* __restrict__ dst, const KP& k, const Ghost& c,
-                                           uint32_t gi, uint32_t wi, int m, bool inlet)
+                                           uint32_t gi, uint32_t wi, bool inlet)
 {
-    typename S::T v[Q];
-    ghost_gather<BC, S>(dst, k, c, wi, m, inlet, v);
-    ghost_scatter<BC, S>(dst, k, c, gi, v);
+    const int sx = c.x < 0 ? 1 : (c.x >= k.nx ? 2 : 0);
+    const int sy = c.y < 0 ? 1 : (c.y >= k.ny ? 2 : 0);
+    const int sz = c.z < 0 ? 1 : (c.z >= k.nz ? 2 : 0);
+    switch (sx * 9 + sy * 3 + sz) {
+#define CGLBM_GHOST_CASE(X, Y, Z) \
+    case X * 9 + Y * 3 + Z: ghost_fill<BC, S, X, Y, Z>(dst, k, c, gi, wi, inlet); break;
+        CGLBM_GHOST_CASE(0, 0, 1) CGLBM_GHOST_CASE(0, 0, 2) CGLBM_GHOST_CASE(0, 1, 0) CGLBM_GHOST_CASE(0, 1, 1)
+        CGLBM_GHOST_CASE(0, 1, 2) CGLBM_GHOST_CASE(0, 2, 0) CGLBM_GHOST_CASE(0, 2, 1) CGLBM_GHOST_CASE(0, 2, 2)
+        CGLBM_GHOST_CASE(1, 0, 0) CGLBM_GHOST_CASE(1, 0, 1) CGLBM_GHOST_CASE(1, 0, 2) CGLBM_GHOST_CASE(1, 1, 0)
+        CGLBM_GHOST_CASE(1, 1, 1) CGLBM_GHOST_CASE(1, 1, 2) CGLBM_GHOST_CASE(1, 2, 0) CGLBM_GHOST_CASE(1, 2, 1)
+        CGLBM_GHOST_CASE(1, 2, 2) CGLBM_GHOST_CASE(2, 0, 0) CGLBM_GHOST_CASE(2, 0, 1) CGLBM_GHOST_CASE(2, 0, 2)
+        CGLBM_GHOST_CASE(2, 1, 0) CGLBM_GHOST_CASE(2, 1, 1) CGLBM_GHOST_CASE(2, 1, 2) CGLBM_GHOST_CASE(2, 2, 0)
+        CGLBM_GHOST_CASE(2, 2, 1) CGLBM_GHOST_CASE(2, 2, 2)
+#undef CGLBM_GHOST_CASE
+    default: break;
+    }
 }
 
 template <int BC, class S>
@@ -832,7 +853,7 @@ __global__ __launch_bounds__(BLOCK) void k_pop_ghosts(typename S::T* __restrict_
     const uint32_t gi = pidx(k, c.x, c.y, c.z);
     if (BC == LBM_BC_PERIODIC) {
         const uint32_t wi = pidx(k, wrapc(c.x, k.nx), wrapc(c.y, k.ny), wrapc(c.z, k.nz));
-        ghost_dirs<BC, S>(dst, k, c, gi, wi, 0, false);
+        ghost_dirs<BC, S>(dst, k, c, gi, wi, false);
         Rout[gi] = Rout[wi];
         if (S::kEqRef) Qout[gi] = Qout[wi];
         return;
@@ -840,7 +861,7 @@ __global__ __launch_bounds__(BLOCK) void k_pop_ghosts(typename S::T* __restrict_
     const bool inlet = c.z < 0 && inlet_inside(k, c.x, c.y);
     const int m = ((c.x < 0 || c.x >= k.nx) ? 1 : 0) | ((c.y < 0 || c.y >= k.ny) ? 2 : 0) | (c.z < 0 ? 4 : 0);
     const uint32_t wi = pidx(k, clampc(c.x, k.nx), clampc(c.y, k.ny), clampc(c.z, k.nz));
-    ghost_dirs<BC, S>(dst, k, c, gi, wi, m, inlet);
+    ghost_dirs<BC, S>(dst, k, c, gi, wi, inlet);
     if (inlet) {
         Rout[gi] = make_float4(frac_tag(0.0, 1u), 0.f, 0.f, 0.f);  // pure red: x_b = 0
         if (S::kEqRef) Qout[gi] = make_uint4(0u, 0u, 0u, 0u);  // zero record: the stored value is the deviation
