@@ -320,19 +320,19 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
             // density pass (jet: the outlet plane by the convective condition)
             if (jet) {
                 const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1)), go(h->grid_dtiles.x, 1);
-                hipLaunchKernelGGL((k_density<S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k);
+                hipLaunchKernelGGL((k_density<BC, S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k);
                 LAUNCH_CHECK();
                 KP ko = k;
                 ko.z0 = h->p.nz - 1;
                 hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, hprev,
                                    hcur, ko);
             } else {
-                hipLaunchKernelGGL((k_density<S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k);
+                hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR,
+                                   k);
             }
             LAUNCH_CHECK();
+            // (the density kernels also fill the field ghost shell)
             if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
-            hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
-            LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
             // fused collide-perturb-recolour-stream
             hipLaunchKernelGGL((k_collide<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,

@@ -562,24 +562,27 @@ __device__ __forceinline__ void load_window(T* __restrict__ win, const T* __rest
 // fields: PD = (phi, rho - rho_b0) per padded node and XR = the minority
 // colour's fraction, tagged (see "colour fractions"), from the mass sum
 // m0 = rho - rho_b0 and the two colour masses.
-__device__ __forceinline__ void store_pd(float2* __restrict__ PD, const KP& k, uint32_t n, double m0, double rr,
-                                         double rb)
+__device__ __forceinline__ float2 store_pd(float2* __restrict__ PD, const KP& k, uint32_t n, double m0, double rr,
+                                           double rb)
 {
     const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
-    stp(PD, n, make_float2((float)((a - b) / (a + b)), (float)m0));  // Eq. order
+    const float2 v = make_float2((float)((a - b) / (a + b)), (float)m0);  // Eq. order
+    stp(PD, n, v);
+    return v;
 }
 
-__device__ __forceinline__ void store_fields_sums(float2* __restrict__ PD, float* __restrict__ XR, const KP& k,
-                                                  uint32_t n, double m0, double rr, double rb)
+__device__ __forceinline__ float2 store_fields_sums(float2* __restrict__ PD, float* __restrict__ XR, const KP& k,
+                                                    uint32_t n, double m0, double rr, double rb)
 {
     const double rho = (double)k.rho_b0 + m0;
-    store_pd(PD, k, n, m0, rr, rb);
+    const float2 v = store_pd(PD, k, n, m0, rr, rb);
     const uint32_t bl = rr > rb;
     stp(XR, n, frac_tag((bl ? rb : rr) / rho, bl));
+    return v;
 }
 
-__device__ __forceinline__ void store_fields(float2* __restrict__ PD, float* __restrict__ XR, const KP& k, uint32_t n,
-                                             const float* d, const float* fr)
+__device__ __forceinline__ float2 store_fields(float2* __restrict__ PD, float* __restrict__ XR, const KP& k,
+                                               uint32_t n, const float* d, const float* fr)
 {
     double m0 = 0.0, rr = 0.0;
 #pragma unroll
@@ -587,7 +590,47 @@ __device__ __forceinline__ void store_fields(float2* __restrict__ PD, float* __r
         m0 += (double)d[i];
         rr += (double)fr[i];
     }
-    store_fields_sums(PD, XR, k, n, m0, rr, (double)k.rho_b0 + m0 - rr);
+    return store_fields_sums(PD, XR, k, n, m0, rr, (double)k.rho_b0 + m0 - rr);
+}
+
+// The (phi, rho - rho_b0) of the ghost shell, written by the node each ghost
+// cell images: periodic copies across the wrap, or (jet) mirrored copies
+// across the half-way walls and the outlet, and (1, rho_r0 - rho_b0) in the
+// inlet circle at z = -1.  Only nodes on a face of the lattice write.
+template <int BC>
+__device__ __forceinline__ void store_pd_ghosts(float2* __restrict__ PD, const KP& k, int x, int y, int z, float2 v)
+{
+    const bool yzf = y == 0 || y == k.ny - 1 || z == 0 || z == k.nz - 1;
+    if (!yzf) {  // the common case: an x face only (every row has two)
+        if (x == 0) stp(PD, pidx(k, BC == LBM_BC_PERIODIC ? k.nx : -1, y, z), v);
+        if (x == k.nx - 1) stp(PD, pidx(k, BC == LBM_BC_PERIODIC ? -1 : k.nx, y, z), v);
+        return;
+    }
+    int ix[3] = {x, 0, 0}, iy[3] = {y, 0, 0}, iz[3] = {z, 0, 0};
+    int nx = 1, ny = 1, nz = 1;
+    if (BC == LBM_BC_PERIODIC) {
+        if (x == 0) ix[nx++] = k.nx;
+        if (x == k.nx - 1) ix[nx++] = -1;
+        if (y == 0) iy[ny++] = k.ny;
+        if (y == k.ny - 1) iy[ny++] = -1;
+        if (z == 0) iz[nz++] = k.nz;
+        if (z == k.nz - 1) iz[nz++] = -1;
+    } else {
+        if (x == 0) ix[nx++] = -1;
+        if (x == k.nx - 1) ix[nx++] = k.nx;
+        if (y == 0) iy[ny++] = -1;
+        if (y == k.ny - 1) iy[ny++] = k.ny;
+        if (z == 0) iz[nz++] = -1;
+        if (z == k.nz - 1) iz[nz++] = k.nz;
+    }
+    if (nx * ny * nz == 1) return;
+    for (int c = 0; c < nz; ++c)
+        for (int b = 0; b < ny; ++b)
+            for (int a = 0; a < nx; ++a) {
+                if ((a | b | c) == 0) continue;
+                const bool in = BC == LBM_BC_JET && iz[c] < 0 && inlet_inside(k, ix[a], iy[b]);
+                stp(PD, pidx(k, ix[a], iy[b], iz[c]), in ? make_float2(1.f, k.rho_r0 - k.rho_b0) : v);
+            }
 }
 
 __host__ __device__ constexpr double inv_lend(int i)
@@ -639,8 +682,8 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
 
 // Density pass over the planes of the grid (for the jet all but the outlet
 // plane, which k_outlet_density takes: its branch would double this kernel's
-// register count and halve its occupancy).
-template <class S>
+// register count and halve its occupancy); also fills the field ghost shell.
+template <int BC, class S>
 __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
                                                      float* __restrict__ XR, KP k)
 {
@@ -653,7 +696,8 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
         accum_general<S>(src, k, nd.n, m0, mk);
         const double mo = (double)k.rho_b0 + m0 - mk;
         const bool bl = blue_kept(ldp(k.R, nd.n).x);
-        store_fields_sums(PD, XR, k, nd.n, m0, bl ? mo : mk, bl ? mk : mo);
+        const float2 v = store_fields_sums(PD, XR, k, nd.n, m0, bl ? mo : mk, bl ? mk : mo);
+        store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
         return;
     }
     load_window<DTY>(win, k.R, k, t);
@@ -672,7 +716,8 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
     m0 = (double)ms;
     const double rho = (double)k.rho_b0 + m0;
     mk = (double)x0 * rho + (double)(cf + (bl ? -cv : cv));
-    store_fields_sums(PD, XR, k, nd.n, m0, bl ? rho - mk : mk, bl ? mk : rho - mk);
+    const float2 v = store_fields_sums(PD, XR, k, nd.n, m0, bl ? rho - mk : mk, bl ? mk : rho - mk);
+    store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
 }
 
 // Jet outlet plane (z = nz - 1, launched with z0 = nz - 1 and one plane): its
@@ -693,7 +738,8 @@ __global__ __launch_bounds__(DBLOCK) void k_outlet_density(const typename S::T* 
         hcur[(size_t)i * k.plane + nd.q] = d[i];
         hcur[(size_t)(Q + i) * k.plane + nd.q] = fr[i];
     }
-    store_fields(PD, XR, k, nd.n, d, fr);
+    const float2 v = store_fields(PD, XR, k, nd.n, d, fr);
+    store_pd_ghosts<LBM_BC_JET>(PD, k, nd.x, nd.y, nd.z, v);
 }
 
 
