@@ -1248,12 +1248,13 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
 
 
 // ---------------------------------------------------------------- fused collide-recolour-stream
-// waves per SIMD, measured on MI355X: four (at most 128 VGPRs) in FP32, FP16
-// and the referenced forms, 7 % faster than three in FP32 (five spill there);
-// five for plain BF16 (96 VGPRs, no spill), 1.4 % faster than four.  Jet: the
-// outlet plane's pre-collision state is the one the density pass recorded.
+// waves per SIMD, measured on MI355X: four (at most 128 VGPRs) in FP32 and
+// the referenced forms, 7 % faster than three in FP32 (five spill there);
+// five for plain BF16 and FP16 (96 VGPRs, no spill), up to 9 % faster than
+// four.  Jet: the outlet plane's pre-collision state is the one the density
+// pass recorded.
 template <class S>
-constexpr int kCollideWaves = (__is_same(typename S::T, uint16_t) && !S::kEqRef) ? 5 : 4;
+constexpr int kCollideWaves = (sizeof(typename S::T) == 2 && !S::kEqRef) ? 5 : 4;
 
 template <int BC, class S>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kCollideWaves<S>, kCollideWaves<S>))) void
@@ -1262,9 +1263,9 @@ k_collide(
     const float* __restrict__ XR, const float* __restrict__ hcur, float4* __restrict__ Rout, uint4* __restrict__ Qout,
     KP k)
 {
-    // FP32 storage: the (phi, rho) stencil from an LDS window (measured faster);
-    // 16-bit storage: from the caches (the window barrier measured slower there)
-    constexpr bool kWin = sizeof(typename S::T) == 4;
+    // the (phi, rho) stencil from an LDS window (measured faster than through
+    // the caches, for the 16-bit forms too at their present occupancy)
+    constexpr bool kWin = true;
     __shared__ float2 win[kWin ? SW : 1];
     const Tile t = this_tile(k);
     const Node& nd = t.nd;
