@@ -331,8 +331,11 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
                                    k);
             }
             LAUNCH_CHECK();
-            // (the density kernels also fill the field ghost shell)
             if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
+            if (!kDensityGhosts<S>) {  // FP32: the density kernels fill the field ghost shell
+                hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
+                LAUNCH_CHECK();
+            }
             if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
             // fused collide-perturb-recolour-stream
             hipLaunchKernelGGL((k_collide<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,

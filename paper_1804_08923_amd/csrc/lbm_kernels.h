@@ -682,7 +682,13 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
 
 // Density pass over the planes of the grid (for the jet all but the outlet
 // plane, which k_outlet_density takes: its branch would double this kernel's
-// register count and halve its occupancy); also fills the field ghost shell.
+// register count and halve its occupancy).  With FP32 storage it also fills
+// the field ghost shell; with 16-bit storage k_field_ghosts does (measured:
+// the ghost writes cost the shorter 16-bit density pass more than the extra
+// launch).
+template <class S>
+constexpr bool kDensityGhosts = sizeof(typename S::T) == 4;
+
 template <int BC, class S>
 __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
                                                      float* __restrict__ XR, KP k)
@@ -697,7 +703,7 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
         const double mo = (double)k.rho_b0 + m0 - mk;
         const bool bl = blue_kept(ldp(k.R, nd.n).x);
         const float2 v = store_fields_sums(PD, XR, k, nd.n, m0, bl ? mo : mk, bl ? mk : mo);
-        store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
+        if constexpr (kDensityGhosts<S>) store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
         return;
     }
     load_window<DTY>(win, k.R, k, t);
@@ -717,7 +723,7 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
     const double rho = (double)k.rho_b0 + m0;
     mk = (double)x0 * rho + (double)(cf + (bl ? -cv : cv));
     const float2 v = store_fields_sums(PD, XR, k, nd.n, m0, bl ? rho - mk : mk, bl ? mk : rho - mk);
-    store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
+    if constexpr (kDensityGhosts<S>) store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
 }
 
 // Jet outlet plane (z = nz - 1, launched with z0 = nz - 1 and one plane): its
@@ -739,7 +745,7 @@ __global__ __launch_bounds__(DBLOCK) void k_outlet_density(const typename S::T* 
         hcur[(size_t)(Q + i) * k.plane + nd.q] = fr[i];
     }
     const float2 v = store_fields(PD, XR, k, nd.n, d, fr);
-    store_pd_ghosts<LBM_BC_JET>(PD, k, nd.x, nd.y, nd.z, v);
+    if constexpr (kDensityGhosts<S>) store_pd_ghosts<LBM_BC_JET>(PD, k, nd.x, nd.y, nd.z, v);
 }
 
 
