@@ -198,6 +198,38 @@ int lbm_profile(lbm_handle* h, int enable);
  * (index 2), and clear them. */
 int lbm_profile_read(lbm_handle* h, double* ms /* 3 */, int64_t* launches /* 3 */);
 
+/* Jet diagnostics of Sec. IV C on the current state (not part of a step;
+ * readings: the jet phase is phi > 0, components are face-connected without
+ * wrap-around, volumes count nodes).
+ *   jet_nodes      nodes with phi > 0 (phi as lbm_macroscopic returns it);
+ *   front_z        the leading edge: largest z of a jet node, -1 if none;
+ *   column_volume  nodes of the components with a node on the inlet plane
+ *                  z = 0 (the continuous column from the nozzle);
+ *   n_fragments    the other components, the fragments; their equivalent
+ *                  diameters are d = (6 V / pi)^(1/3) of their volumes V. */
+typedef struct lbm_jet_stats {
+    int64_t jet_nodes;
+    int64_t front_z;
+    int64_t column_volume;
+    int64_t n_fragments;
+} lbm_jet_stats;
+
+/* Bytes of the device work buffer lbm_jet_diagnostics needs (16 per node
+ * plus a 256-byte header). */
+int lbm_diag_bytes(const lbm_params* p, uint64_t* bytes);
+
+/* Compute the jet diagnostics of the current state.
+ *   work     device, lbm_diag_bytes() bytes, 256-byte aligned, caller-owned
+ *            (contents on entry do not matter; overwritten);
+ *   stats    HOST, filled;
+ *   volumes  HOST, cap entries (may be NULL when cap == 0): the volumes of
+ *            the first min(n_fragments, cap) fragments, in no particular
+ *            order.
+ * Enqueued on the handle's stream; synchronises the host before returning.
+ * Connected components come from a lock-free union-find (atomic minimum on
+ * parent indices); the result does not depend on the order of the atomics. */
+int lbm_jet_diagnostics(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, int64_t cap);
+
 /* Release the handle (not the caller's buffers).  NULL is accepted. */
 int lbm_destroy(lbm_handle* h);
 

@@ -3,11 +3,13 @@
 // caller; this file never allocates it.
 #include <stdarg.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
 
 #include "lbm_adjoint.h"
+#include "lbm_diag.h"
 #include "lbm_kernels.h"
 
 using namespace cglbm;
@@ -506,6 +508,60 @@ int lbm_destroy(lbm_handle* h)
     if (h)
         for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
+    return LBM_OK;
+}
+
+int lbm_diag_bytes(const lbm_params* p, uint64_t* bytes)
+{
+    if (!bytes) return fail(LBM_ERR_INVALID_ARG, "bytes is NULL");
+    const int rc = validate(p);
+    if (rc != LBM_OK) return rc;
+    *bytes = diag_bytes((uint64_t)p->nx * p->ny * p->nz);
+    return LBM_OK;
+}
+
+int lbm_jet_diagnostics(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (!work || !stats) return fail(LBM_ERR_INVALID_ARG, "work and stats are required");
+    if (!aligned(work, 256)) return fail(LBM_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    if (cap < 0 || (cap > 0 && !volumes)) return fail(LBM_ERR_INVALID_ARG, "volumes is NULL with cap > 0");
+    const KP k = read_kp(h);
+    const DiagWork w = diag_layout(work, k.N);
+    int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
+        using S = decltype(st);
+        constexpr int BC = decltype(bc)::value;
+        hipLaunchKernelGGL(k_diag_clear, dim3(1), dim3(64), 0, h->stream, w);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_diag_init<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                           (const typename S::T*)h->pop[h->cur], h->hist[h->hprev], k, w);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_diag_merge, h->grid_all, dim3(BLOCK), 0, h->stream, k, w);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_diag_flatten, h->grid_all, dim3(BLOCK), 0, h->stream, k, w);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_diag_count, h->grid_all, dim3(BLOCK), 0, h->stream, k, w);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_diag_collect, h->grid_all, dim3(BLOCK), 0, h->stream, k, w);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    });
+    if (rc != LBM_OK) return rc;
+    DiagHeader hd;
+    HIP_CHECK(hipMemcpyAsync(&hd, w.hdr, sizeof(hd), hipMemcpyDeviceToHost, h->stream));
+    HIP_CHECK(hipStreamSynchronize(h->stream));
+    if (hd.overflow) return fail(LBM_ERR_HIP, "connected-component walk exceeded its bound");
+    stats->jet_nodes = (int64_t)hd.jet_nodes;
+    stats->front_z = hd.front_z;
+    stats->column_volume = (int64_t)hd.column_volume;
+    stats->n_fragments = hd.n_fragments;
+    const int64_t n = std::min<int64_t>(cap, (int64_t)hd.n_fragments);
+    if (n > 0) {
+        std::vector<int> v((size_t)n);
+        HIP_CHECK(hipMemcpyAsync(v.data(), w.volume, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIP_CHECK(hipStreamSynchronize(h->stream));
+        for (int64_t i = 0; i < n; ++i) volumes[i] = v[(size_t)i];
+    }
     return LBM_OK;
 }
 

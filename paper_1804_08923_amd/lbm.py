@@ -49,14 +49,18 @@ class lbm_sizes(C.Structure):
                                           "inlet_bytes", "adjoint_bytes", "state_bytes")]
 
 
+class lbm_jet_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("jet_nodes", "front_z", "column_volume", "n_fragments")]
+
+
 class lbm_buffers(C.Structure):
     _fields_ = [("pop_a", C.c_void_p), ("pop_b", C.c_void_p), ("fields", C.c_void_p), ("hist", C.c_void_p),
                 ("audit", C.c_void_p), ("inlet_uz", C.c_void_p), ("adjoint", C.c_void_p)]
 
 
 EXPORTS = ("lbm_query_sizes", "lbm_init", "lbm_step", "lbm_macroscopic", "lbm_get_state", "lbm_set_state",
-           "lbm_time", "lbm_adjoint_step", "lbm_profile", "lbm_profile_read", "lbm_destroy", "lbm_status_string",
-           "lbm_last_error")
+           "lbm_time", "lbm_adjoint_step", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
+           "lbm_profile_read", "lbm_destroy", "lbm_status_string", "lbm_last_error")
 
 _lib = None
 
@@ -79,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_time.argtypes = [vp]
     lib.lbm_time.restype = i64
     lib.lbm_adjoint_step.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
+    lib.lbm_diag_bytes.argtypes = [C.POINTER(lbm_params), C.POINTER(C.c_uint64)]
+    lib.lbm_jet_diagnostics.argtypes = [vp, vp, C.POINTER(lbm_jet_stats), C.POINTER(C.c_int64), C.c_int64]
     lib.lbm_profile.argtypes = [vp, C.c_int]
     lib.lbm_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.lbm_destroy.argtypes = [vp]
@@ -86,7 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_status_string.restype = C.c_char_p
     lib.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_query_sizes", "lbm_init", "lbm_step", "lbm_macroscopic", "lbm_get_state",
-                 "lbm_set_state", "lbm_adjoint_step", "lbm_profile", "lbm_profile_read", "lbm_destroy"):
+                 "lbm_set_state", "lbm_adjoint_step", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
+                 "lbm_profile_read", "lbm_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -214,6 +221,24 @@ class LBM:
             assert dJ_du_in.dtype == self.torch.float32 and dJ_du_in.numel() == self.prob.nx * self.prob.ny
         _check(self.lib, self.lib.lbm_adjoint_step(self.h, state_t.data_ptr(), int(t), lam_in.data_ptr(),
                                                    lam_out.data_ptr(), dJ_dA.data_ptr(), _ptr(dJ_du_in)))
+
+    def jet_diagnostics(self, cap: Optional[int] = None):
+        """Leading edge and fragments of the jet phase (lbm_jet_diagnostics):
+        a dict of the four statistics and the fragment volumes (numpy int64,
+        sorted in descending order; at most ``cap`` of them, all by default)."""
+        import numpy as np
+        torch = self.torch
+        if getattr(self, "_diag_work", None) is None:
+            nb = C.c_uint64()
+            _check(self.lib, self.lib.lbm_diag_bytes(C.byref(self.params), C.byref(nb)))
+            self._diag_work = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        st = lbm_jet_stats()
+        cap = self.sizes.n_nodes if cap is None else int(cap)
+        vol = (C.c_int64 * max(cap, 1))()
+        _check(self.lib, self.lib.lbm_jet_diagnostics(self.h, self._diag_work.data_ptr(), C.byref(st), vol, cap))
+        n = min(cap, st.n_fragments)
+        v = np.sort(np.frombuffer(vol, dtype=np.int64, count=n))[::-1].copy()
+        return {k: int(getattr(st, k)) for k, _ in lbm_jet_stats._fields_}, v
 
     def profile(self, enable: bool = True):
         _check(self.lib, self.lib.lbm_profile(self.h, 1 if enable else 0))

@@ -37,6 +37,25 @@ def smooth_velocity(nx, ny, nz, seed, amp=0.02):
     return u.reshape(-1, 3)
 
 
+def sphere_blobs(nx, ny, nz, seed, n_blobs, r_min=0.8, r_max=4.0):
+    """An order-parameter-like field (node order) of +-1 with values in
+    [0.3, 1] inside n_blobs random spheres (some overlapping, some cut by the
+    lattice faces) and in [-1, -0.3] outside: many connected components with
+    no value near 0."""
+    rng = np.random.default_rng(seed)
+    inside = np.zeros((nz, ny, nx), bool)
+    cs = rng.uniform([0, 0, 0], [nx, ny, nz], size=(n_blobs, 3))
+    rs = rng.uniform(r_min, r_max, size=n_blobs)
+    for c, r in zip(cs, rs):
+        lo = np.maximum(np.floor(c - r).astype(int), 0)
+        hi = np.minimum(np.ceil(c + r).astype(int) + 1, [nx, ny, nz])
+        z, y, x = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]), np.arange(lo[0], hi[0]),
+                              indexing="ij")
+        inside[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2 < r * r
+    mag = rng.uniform(0.3, 1.0, size=inside.shape)
+    return np.where(inside, mag, -mag).ravel()
+
+
 def population_noise(n_nodes, seed, amp=1e-4):
     """Independent noise for the 2 x 27 populations of every node."""
     rng = np.random.default_rng(seed + 13)

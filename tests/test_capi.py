@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(lbm.EXPORTS)
-    assert len(names) == 13
+    assert len(names) == 15
 
 
 def test_query_sizes(lib):
