@@ -62,7 +62,7 @@ def measured_traffic(storage):
     return ent.get("bytes_per_launch")
 
 
-def run_leg(prob, steps, warmup):
+def run_leg(prob, steps, warmup, diagnostics=False):
     import torch
 
     from paper_1804_08923_amd.lbm import LBM
@@ -97,6 +97,16 @@ def run_leg(prob, steps, warmup):
     umax = float(m["u"].norm(dim=1).max().item())
     finite = bool(torch.isfinite(m["u"]).all().item())
     del m
+    diag = None
+    if diagnostics:
+        # jet diagnostics (leading edge, fragments) of the final state, timed
+        # on the host clock around the synchronising call
+        sim.jet_diagnostics()
+        reps = 5
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            stats, vol = sim.jet_diagnostics()
+        diag = dict(ms=round((time.perf_counter() - t1) / reps * 1e3, 3), step=warmup + steps, **stats)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -105,7 +115,7 @@ def run_leg(prob, steps, warmup):
     avg_fused = kms[1] / launches[1]
     avg_dens = kms[0] / launches[0]
     achieved = FUSED_BYTES[st] * N / (avg_fused * 1e-3) / 1e9
-    return dict(mlups=mlups, ms_per_step=ms / steps, wall_s=wall, umax=umax, finite=finite, audit=audit,
+    return dict(mlups=mlups, ms_per_step=ms / steps, wall_s=wall, umax=umax, finite=finite, audit=audit, diag=diag,
                 fused_ms=avg_fused, density_ms=avg_dens, boundary_ms=bnd, fused_gbs=achieved,
                 step_roofline_frac=mlups / (HBM_PEAK_GBS * 1e9 / STEP_BYTES[st] / 1e6))
 
@@ -204,10 +214,11 @@ def main():
         torch.cuda.empty_cache()
         log("bench: copy probe (1 GiB read + 1 GiB write) done")
 
-    main_leg = run_leg(prob, args.steps, args.warmup)
+    main_leg = run_leg(prob, args.steps, args.warmup, diagnostics=True)
     log(f"bench: fp32 {main_leg['mlups']:.0f} MLUPS, fused kernel {main_leg['fused_ms']:.3f} ms "
         f"({main_leg['fused_gbs']:.0f} GB/s), density {main_leg['density_ms']:.3f} ms, "
         f"boundary {main_leg['boundary_ms']:.3f} ms")
+    log(f"bench: jet diagnostics {main_leg['diag']}")
     legs = {}
     if not args.no_legs:
         for st in ("bf16", "fp16", "bf16eq", "fp16eq"):
@@ -259,6 +270,7 @@ def main():
         "impl_bytes_per_node": FUSED_BYTES["fp32"] + DENSITY_BYTES["fp32"],
         "density_kernel_ms": round(main_leg["density_ms"], 4),
         "boundary_kernels_ms": round(main_leg["boundary_ms"], 4),
+        "jet_diagnostics": main_leg["diag"],
         "cpu_baseline": cpu,
         "storage_legs": legs,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,

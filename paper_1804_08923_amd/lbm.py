@@ -233,9 +233,15 @@ class LBM:
             _check(self.lib, self.lib.lbm_diag_bytes(C.byref(self.params), C.byref(nb)))
             self._diag_work = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
         st = lbm_jet_stats()
-        cap = self.sizes.n_nodes if cap is None else int(cap)
+        want = cap is None
+        cap = min(self.sizes.n_nodes, 1 << 16) if want else int(cap)
         vol = (C.c_int64 * max(cap, 1))()
         _check(self.lib, self.lib.lbm_jet_diagnostics(self.h, self._diag_work.data_ptr(), C.byref(st), vol, cap))
+        if want and st.n_fragments > cap:  # all of them were asked for: again with room for every one
+            cap = st.n_fragments
+            vol = (C.c_int64 * cap)()
+            _check(self.lib, self.lib.lbm_jet_diagnostics(self.h, self._diag_work.data_ptr(), C.byref(st), vol,
+                                                          cap))
         n = min(cap, st.n_fragments)
         v = np.sort(np.frombuffer(vol, dtype=np.int64, count=n))[::-1].copy()
         return {k: int(getattr(st, k)) for k, _ in lbm_jet_stats._fields_}, v
