@@ -127,10 +127,26 @@ def jet_64() -> Problem:
                        noise_amp=0.0)
 
 
+# The UT melt-jet cases of Sec. IV B (Table II): an 8 D x 8 D x 40 D lattice
+# with D = 30, u = 0.05, gamma = 8.3, eta = 0.54, and the case's Re, We, Fr.
+UT_CASES = {1: (6.1e4, 2.3e2, 64.0), 2: (6.5e4, 1.8e2, 24.0), 3: (1.1e5, 3.3e2, 20.0), 4: (1.5e5, 4.5e2, 16.0)}
+
+
+def jet_ut(case: int) -> Problem:
+    """UT case `case` at the paper's resolution (240x240x1200, 69 M nodes),
+    20 000 steps, 1 % inlet noise."""
+    Re, We, Fr = UT_CASES[case]
+    return jet_problem(f"jet-ut{case}-240x240x1200", 240, 240, 1200, 30, 0.05, 8.3, 0.54, Re, We, Fr, 20000)
+
+
 WORKLOADS = {
     "droplet-32": droplet_small,
     "droplet-32-cm": droplet_cm,
     "jet-128x128x512": jet_128,
     "jet-256x256x1024": jet_256,
     "jet-64x64x256": jet_64,
+    "jet-ut1-240x240x1200": lambda: jet_ut(1),
+    "jet-ut2-240x240x1200": lambda: jet_ut(2),
+    "jet-ut3-240x240x1200": lambda: jet_ut(3),
+    "jet-ut4-240x240x1200": lambda: jet_ut(4),
 }

@@ -80,3 +80,12 @@ def test_equivalent_diameter_of_a_sphere_and_mass_median():
     assert np.isclose(mass_median_diameter([1, 8, 1]), equivalent_diameter(8))
     # volumes 4, 4, 1, 1: cumulative (1, 2, 6, 10) reaches 5 at the first 4
     assert np.isclose(mass_median_diameter([4, 1, 4, 1]), equivalent_diameter(4))
+
+
+def test_run_jet_mass_median_matches_the_oracle():
+    from paper_1804_08923_amd.run_jet import mass_median
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 5, 40):
+        v = rng.integers(1, 500, size=n)
+        assert np.isclose(mass_median(v), mass_median_diameter(v), rtol=1e-12)
+    assert np.isnan(mass_median([]))
