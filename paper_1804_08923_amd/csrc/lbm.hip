@@ -91,9 +91,9 @@ int validate(const lbm_params* p)
         return fail(LBM_ERR_INVALID_ARG, "lattice %dx%dx%d too small (min %d)", p->nx, p->ny, p->nz, minn);
     if (p->nx > 65535 || p->ny > 65535 || p->nz > 65535)
         return fail(LBM_ERR_UNSUPPORTED, "a lattice dimension above 65535");
-    // 32-bit byte offsets of a float4 per padded node
-    if ((double)padded_nodes(p) * 16.0 > 4294967295.0)
-        return fail(LBM_ERR_UNSUPPORTED, "more than 2^28 padded nodes");
+    // 32-bit byte offsets of a float2 per padded node
+    if ((double)padded_nodes(p) * 8.0 > 4294967295.0)
+        return fail(LBM_ERR_UNSUPPORTED, "more than 2^29 padded nodes");
     if (!(p->nu_r > 0) || !(p->nu_b > 0)) return fail(LBM_ERR_INVALID_ARG, "viscosities must be > 0");
     if (!(p->rho_r0 > 0) || !(p->rho_b0 > 0)) return fail(LBM_ERR_INVALID_ARG, "reference densities must be > 0");
     if (!(p->alpha_b > 0 && p->alpha_b < 1)) return fail(LBM_ERR_INVALID_ARG, "alpha_b must lie in (0, 1)");

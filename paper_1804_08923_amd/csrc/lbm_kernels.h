@@ -168,16 +168,23 @@ __device__ __forceinline__ Node this_node(const KP& k)
     return d;
 }
 
-// element idx of a plane, addressed as uniform base + 32-bit byte offset
+// element idx of a plane, addressed as uniform base + byte offset (32-bit for
+// elements of up to 8 bytes: at most 2^29 padded nodes)
 template <class T>
 __device__ __forceinline__ T ldp(const T* __restrict__ base, uint32_t idx)
 {
-    return *(const T*)((const char*)base + (idx * (uint32_t)sizeof(T)));
+    if constexpr (sizeof(T) >= 16)  // 16-byte records: 64-bit offsets (more than 2^28 nodes)
+        return *(const T*)((const char*)base + (size_t)idx * sizeof(T));
+    else
+        return *(const T*)((const char*)base + (idx * (uint32_t)sizeof(T)));
 }
 template <class T>
 __device__ __forceinline__ void stp(T* __restrict__ base, uint32_t idx, T v)
 {
-    *(T*)((char*)base + (idx * (uint32_t)sizeof(T))) = v;
+    if constexpr (sizeof(T) >= 16)
+        *(T*)((char*)base + (size_t)idx * sizeof(T)) = v;
+    else
+        *(T*)((char*)base + (idx * (uint32_t)sizeof(T))) = v;
 }
 
 // Population planes through buffer resources: the plane's base address sits
@@ -192,17 +199,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* base, uint
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)(elems * (uint32_t)sizeof(T)),
                                              0x00020000);
 }
-// element n - off of plane p
+// element n - off of plane p (2- or 4-byte elements)
 template <class T>
 __device__ __forceinline__ T ldpl(const T* __restrict__ p, int off, uint32_t NP, uint32_t n)
 {
+    static_assert(sizeof(T) == 2 || sizeof(T) == 4, "population planes hold 2- or 4-byte values");
     const auto r = plane_rsrc(p - off, NP + (uint32_t)(off < 0 ? -off : off));
     const uint32_t b = n * (uint32_t)sizeof(T);
-    if constexpr (sizeof(T) == 16)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, b, 0, 0));
-    else if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, b, 0, 0));
-    else if constexpr (sizeof(T) == 4)
+    if constexpr (sizeof(T) == 4)
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, b, 0, 0));
     else
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, b, 0, 0));
@@ -282,7 +286,7 @@ __device__ __forceinline__ float load_dev(const typename S::T* __restrict__ src,
         const uint32_t lo = __builtin_bit_cast(uint16_t, ldpl(src + (size_t)Q * k.NP, off, k.NP, n));
         return __uint_as_float((hi << 16) | lo);
     } else {
-        const RefRec r = dec_ref<S>(ldpl(k.Qrec, off, k.NP, n));
+        const RefRec r = dec_ref<S>(ldp(k.Qrec, n - (uint32_t)off));
         const float cu = kCX[I] * r.ux + kCY[I] * r.uy + kCZ[I] * r.uz;
         const float u2 = r.ux * r.ux + r.uy * r.uy + r.uz * r.uz;
         return S::dec(ldpl(src + (size_t)I * k.NP, off, k.NP, n)) + wgt(I) * (r.e + r.rho * eq_poly(cu, u2));

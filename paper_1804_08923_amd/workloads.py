@@ -139,6 +139,15 @@ def jet_ut(case: int) -> Problem:
     return jet_problem(f"jet-ut{case}-240x240x1200", 240, 240, 1200, 30, 0.05, 8.3, 0.54, Re, We, Fr, 20000)
 
 
+def jet_ft(fine: bool) -> Problem:
+    """FT T1 (Sec. IV D, Table IV): an 8 D x 8 D x 20 D lattice, D = 30 (coarse,
+    240x240x600, 34.6 M nodes) or D = 60 (fine, 480x480x1200, 276 M nodes);
+    u = 0.05, gamma = 10.1, eta = 1.4, Re = 1.1e6, We = 9.3e4, Fr = 200."""
+    D = 60 if fine else 30
+    return jet_problem(f"jet-ft-{'fine' if fine else 'coarse'}-{8 * D}x{8 * D}x{20 * D}", 8 * D, 8 * D, 20 * D, D,
+                       0.05, 10.1, 1.4, 1.1e6, 9.3e4, 200.0, 20000)
+
+
 WORKLOADS = {
     "droplet-32": droplet_small,
     "droplet-32-cm": droplet_cm,
@@ -149,4 +158,6 @@ WORKLOADS = {
     "jet-ut2-240x240x1200": lambda: jet_ut(2),
     "jet-ut3-240x240x1200": lambda: jet_ut(3),
     "jet-ut4-240x240x1200": lambda: jet_ut(4),
+    "jet-ft-coarse-240x240x600": lambda: jet_ft(False),
+    "jet-ft-fine-480x480x1200": lambda: jet_ft(True),
 }
