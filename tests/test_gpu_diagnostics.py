@@ -57,6 +57,25 @@ def test_fragments_random_blobs(torch, shape, seed, n):
     sim.close()
 
 
+@pytest.mark.parametrize("storage", ["bf16", "fp16eq"])
+def test_fragments_16bit_storage(torch, storage):
+    """The diagnostics read the state through the same decoders as the step."""
+    from synth import sphere_blobs
+
+    from paper_1804_08923_amd.lbm import LBM
+    nx, ny, nz = 40, 36, 50
+    phi = sphere_blobs(nx, ny, nz, 5, 150)
+    prob = Problem(name="blobs16", nx=nx, ny=ny, nz=nz, bc="periodic", rho_r0=1.0, rho_b0=0.5, init="fields",
+                   storage=storage)
+    sim = LBM(prob, rho_r=torch.from_numpy((prob.rho_r0 * (1 + phi) / 2).astype(np.float32)),
+              rho_b=torch.from_numpy((prob.rho_b0 * (1 - phi) / 2).astype(np.float32)))
+    say(f"diagnostics, random blobs, {storage} storage")
+    _compare(sim, prob, storage)
+    sim.step(3)  # and on a shifted state
+    _compare(sim, prob, f"{storage} after 3 steps")
+    sim.close()
+
+
 def test_fragments_full_lattice(torch):
     sim, prob = _blobs(torch, 128, 128, 512, seed=11, n_blobs=20000, bc="jet")
     say("diagnostics, random blobs on the 128x128x512 lattice")
