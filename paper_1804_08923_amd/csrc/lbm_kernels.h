@@ -222,6 +222,20 @@ __device__ __forceinline__ void stpl(T* __restrict__ p, uint32_t NP, uint32_t n,
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, n * 2u, 0, 0);
 }
 
+// 16-byte record (R, reference record) of node n, which lies in padded plane
+// z + 1 (n or a neighbour in the same row), stored through a buffer resource
+// based at that plane: the per-lane offset stays within one plane (32 bits
+// for any lattice), so the store needs no 64-bit per-lane address.
+template <class T>
+__device__ __forceinline__ void st_rec(T* __restrict__ base, const KP& k, int z, uint32_t n, T v)
+{
+    static_assert(sizeof(T) == 16, "16-byte records");
+    const uint32_t pp = (uint32_t)k.px * (uint32_t)k.py, p0 = (uint32_t)(z + 1) * pp;
+    const auto r = plane_rsrc(base + p0, pp);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, v), r,
+                                           (n - p0) * 16u, 0, 0);
+}
+
 // ---------------------------------------------------------------- 16-bit storage
 // In the plain 16-bit forms the stored deviation d_i = f_i - w_i rho_b0 of a
 // moving direction carries the velocity part of the equilibrium,
@@ -1016,12 +1030,12 @@ __device__ __forceinline__ void ghost_R_x(const KP& k, const Node& nd, float4* _
                                           bool xh)
 {
     if (BC == LBM_BC_PERIODIC) {
-        if (xh) stp(Rout, nd.n - (uint32_t)k.nx, r);
-        if (xl) stp(Rout, nd.n + (uint32_t)k.nx, r);
+        if (xh) st_rec(Rout, k, nd.z, nd.n - (uint32_t)k.nx, r);
+        if (xl) st_rec(Rout, k, nd.z, nd.n + (uint32_t)k.nx, r);
     } else {
         const float4 m = make_float4(r.x, -r.y, r.z, r.w);
-        if (xl) stp(Rout, nd.n - 1u, m);
-        if (xh) stp(Rout, nd.n + 1u, m);
+        if (xl) st_rec(Rout, k, nd.z, nd.n - 1u, m);
+        if (xh) st_rec(Rout, k, nd.z, nd.n + 1u, m);
     }
 }
 
@@ -1031,12 +1045,12 @@ __device__ __forceinline__ void ghost_Q_x(const KP& k, const Node& nd, uint4* __
                                           bool xh)
 {
     if (BC == LBM_BC_PERIODIC) {
-        if (xh) stp(Qout, nd.n - (uint32_t)k.nx, q);
-        if (xl) stp(Qout, nd.n + (uint32_t)k.nx, q);
+        if (xh) st_rec(Qout, k, nd.z, nd.n - (uint32_t)k.nx, q);
+        if (xl) st_rec(Qout, k, nd.z, nd.n + (uint32_t)k.nx, q);
     } else {
         const uint4 m = mirror_ref(q, 1);
-        if (xl) stp(Qout, nd.n - 1u, m);
-        if (xh) stp(Qout, nd.n + 1u, m);
+        if (xl) st_rec(Qout, k, nd.z, nd.n - 1u, m);
+        if (xh) st_rec(Qout, k, nd.z, nd.n + 1u, m);
     }
 }
 
@@ -1178,7 +1192,7 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
     // recolouring vector V = beta (rho_r rho_b / rho) kappa n (x_r x_b = xk (1 - xk))
     const float rec = k.beta * xk * (1.f - xk) * rhof * (float)kap * inv_gn;
     const float4 rv = make_float4(xk, rec * gpx, rec * gpy, rec * gpz);
-    stp(Rout, n, rv);
+    st_rec(Rout, k, nd.z, n, rv);
     const float nub9 = 9.f * nubf;
     const bool xl = nd.x == 0, xh = nd.x == k.nx - 1;
     const bool yz_edge = nd.y == 0 || nd.y == k.ny - 1 || nd.z == 0 || nd.z == k.nz - 1;
@@ -1187,7 +1201,7 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
     float rt = 0.f, uxt = 0.f, uyt = 0.f, uzt = 0.f, et = 0.f;
     if constexpr (S::kEqRef) {
         const uint4 qr = enc_ref<S>(rhof, uxf, uyf, uzf, (float)E1);
-        stp(Qout, n, qr);
+        st_rec(Qout, k, nd.z, n, qr);
         if (!yz_edge) ghost_Q_x<BC>(k, nd, Qout, qr, xl, xh);
         const RefRec r = dec_ref<S>(qr);
         rt = r.rho;
