@@ -321,13 +321,12 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
             }
             // density pass (jet: the outlet plane by the convective condition)
             if (jet) {
-                const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1)), go(h->grid_dtiles.x, 1);
+                const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1));
+                const dim3 go((unsigned)((h->k.plane + OBLOCK - 1) / OBLOCK));
                 hipLaunchKernelGGL((k_density<BC, S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k);
                 LAUNCH_CHECK();
-                KP ko = k;
-                ko.z0 = h->p.nz - 1;
-                hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, hprev,
-                                   hcur, ko);
+                hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(OBLOCK), 0, h->stream, src, h->PD, h->XR, hprev,
+                                   hcur, k);
             } else {
                 hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR,
                                    k);

@@ -744,17 +744,26 @@ __global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restr
     if constexpr (kDensityGhosts<S>) store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
 }
 
-// Jet outlet plane (z = nz - 1, launched with z0 = nz - 1 and one plane): its
-// state by the convective condition, recorded in hcur for the collision.
+// Jet outlet plane (z = nz - 1): its state by the convective condition,
+// recorded in hcur for the collision.  One plane only, so the launch uses
+// small blocks (OBLOCK lanes) to spread the latency-bound work over many CUs.
+constexpr int OBLOCK = 64;
+
 template <class S>
-__global__ __launch_bounds__(DBLOCK) void k_outlet_density(const typename S::T* __restrict__ src,
+__global__ __launch_bounds__(OBLOCK) void k_outlet_density(const typename S::T* __restrict__ src,
                                                             float2* __restrict__ PD, float* __restrict__ XR,
                                                             const float* __restrict__ hprev, float* __restrict__ hcur,
                                                             KP k)
 {
-    const Tile t = this_tile<DTY>(k);
-    const Node& nd = t.nd;
-    if (!nd.valid) return;
+    const uint32_t q = blockIdx.x * OBLOCK + threadIdx.x;
+    if (q >= k.plane) return;
+    Node nd;
+    nd.z = k.nz - 1;
+    nd.y = (int)(((uint64_t)q * k.nx_mul) >> k.nx_sh);
+    nd.x = (int)q - nd.y * k.nx;
+    nd.q = q;
+    nd.valid = true;
+    nd.n = pidx(k, nd.x, nd.y, nd.z);
     float d[Q], fr[Q], fb[Q];
     outlet_state<S>(src, k, hprev, nd, d, fr, fb);
 #pragma unroll
