@@ -192,7 +192,7 @@ def main():
                     help="also run a 1 GiB device copy (calibrates hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the step is not sharded across GPUs in this build "
+        print("bench.py measures one GPU: the step is not sharded across GPUs "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -128,7 +128,7 @@ class Oracle:
         L.or_noise.restype = C.c_double
         L.or_num_threads.restype = C.c_int
 
-    # scalar argument type of this build (complex is passed as a 2-double struct)
+    # scalar argument type of this variant (complex is passed as a 2-double struct)
     def _scalar_t(self):
         if self.kind == "cs":
             class _Cplx(C.Structure):

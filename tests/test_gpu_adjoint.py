@@ -11,7 +11,7 @@ parameter gradients <w, dS/dA> and <w, dS/du_in>.  Checked:
   * a checkpointed multi-step gradient through the torch.autograd binding
     against complex step and central differences of the FP64 oracle.
 Tolerances: the adjoint runs in FP64 per node with FP32 storage of the
-cotangents, so single-step results agree to ~1e-6 relative; the north-star
+cotangents, so single-step results agree to ~1e-6 relative; the target
 bar for gradients is 1e-4 relative.
 """
 import numpy as np

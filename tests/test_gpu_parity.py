@@ -2,7 +2,7 @@
 
 Element-by-element comparisons on seeded inputs at sizes the oracle finishes
 in seconds (several 256-node blocks plus a ragged tail).  Tolerances: the
-spec bar rel L-inf <= 1e-5 on density and velocity after 200 steps of
+target rel L-inf <= 1e-5 on density and velocity after 200 steps of
 the 32^3 droplet; single steps are compared population by population.
 """
 import numpy as np

@@ -8,7 +8,7 @@ arithmetic) through the C ABI.
   conversions (the library encodes with the gfx950 conversion instructions).
 * Error against the FP64 oracle, per field (rho, u, phi), for every storage
   form on a jet with the same boundaries, buoyancy and inlet noise as the
-  128x128x512 workload, at steps 100 and 300.  Spec bound: velocity
+  128x128x512 workload, at steps 100 and 300.  Accuracy target: velocity
   error <= 1e-3 u_max; met by FP32 and the equilibrium-referenced FP16 form.
 """
 import numpy as np
@@ -93,7 +93,7 @@ def test_storage_error_vs_oracle(torch, orc):
                 f"phi {e['phi']:.2e}")
         sim.close()
     # Bounds: FP32 to its storage floor; the equilibrium-referenced FP16 form
-    # meets the benchmark spec's bound u error <= 1e-3 u_max.  The others do not, and
+    # meets the accuracy target u error <= 1e-3 u_max.  The others do not, and
     # are held to the levels measured on MI355X (regression bounds): plain
     # BF16 / FP16 round the equilibrium's velocity part of every stored
     # deviation (~1.7e-2 / ~1.1e-3 after 100 steps); referenced BF16 still
