@@ -10,8 +10,6 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("lbm_kernels.h", "lbm_lattice.h", "lbm_adjoint.h")] + [
-    os.path.join(ROOT, "include", "cglbm.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

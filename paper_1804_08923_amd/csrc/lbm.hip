@@ -343,8 +343,8 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
                                hcur, Rout, Qout, k);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[3], h->stream));
-            hipLaunchKernelGGL((k_pop_ghosts<BC, S>), h->grid_shell, dim3(BLOCK), 0, h->stream, dst, Rout, Qout, k,
-                               h->ncells);
+            hipLaunchKernelGGL((k_pop_ghosts<BC, S>), dim3((h->ncells + GBLOCK - 1) / GBLOCK), dim3(GBLOCK), 0,
+                               h->stream, dst, Rout, Qout, k, h->ncells);
             LAUNCH_CHECK();
             if (e) HIP_CHECK(hipEventRecord(e[4], h->stream));
             h->cur ^= 1;
