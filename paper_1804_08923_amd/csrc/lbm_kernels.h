@@ -724,9 +724,17 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
 template <class S>
 constexpr bool kDensityGhosts = sizeof(typename S::T) == 4;
 
+// Waves per SIMD the density pass is compiled for.  The plain 16-bit forms
+// ask for eight (LDS allows four 512-lane blocks per CU): measured 184 -> 177
+// us (BF16) and 186 -> 184 us (FP16) on the 128x128x512 jet.  The FP32 and
+// referenced forms were slower at eight; a minimum of two leaves their code as
+// the compiler chooses for 512-lane blocks.
+template <class S>
+constexpr int kDensityWaves = (sizeof(typename S::T) == 2 && !S::kEqRef) ? 8 : 2;
+
 template <int BC, class S>
-__global__ __launch_bounds__(DBLOCK) void k_density(const typename S::T* __restrict__ src, float2* __restrict__ PD,
-                                                     float* __restrict__ XR, KP k)
+__global__ __launch_bounds__(DBLOCK) __attribute__((amdgpu_waves_per_eu(kDensityWaves<S>, 8))) void k_density(
+    const typename S::T* __restrict__ src, float2* __restrict__ PD, float* __restrict__ XR, KP k)
 {
     __shared__ float4 win[TileShape<DTY>::W];
     const Tile t = this_tile<DTY>(k);
