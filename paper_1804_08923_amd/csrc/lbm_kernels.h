@@ -539,7 +539,14 @@ template <int TY = STY>
 __device__ __forceinline__ Tile this_tile(const KP& k)
 {
     Tile t;
-    const int ty = (int)blockIdx.x / k.ntx, tx = (int)blockIdx.x - ty * k.ntx;
+    // XCD-aware order: workgroups go round-robin to the 8 XCDs, so a plane's
+    // neighbouring tiles would sit on different L2s, each fetching the halo
+    // rows they share.  When the plane's tile count is a multiple of 8, XCD j
+    // takes the contiguous band of tiles [j T/8, (j+1) T/8) of every plane (a
+    // bijection; tile t of planes z and z + 1 stays on one XCD either way).
+    uint32_t b = blockIdx.x;
+    if ((gridDim.x & 7u) == 0) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
+    const int ty = (int)b / k.ntx, tx = (int)b - ty * k.ntx;
     t.x0 = tx * STX;
     t.y0 = ty * TY;
     t.z = (int)blockIdx.y + k.z0;
