@@ -570,16 +570,39 @@ __device__ __forceinline__ int wslot(int lx, int ly, int dx, int dy, int dz)
 }
 
 // stage field f over the window of tile t (padded cells beyond the ghost
-// shell of a ragged last tile are skipped: no valid node reads them)
-template <int TY = STY, class T>
+// shell of a ragged last tile are skipped: no valid node reads them).
+// BATCH issues all of a lane's loads before its LDS writes: one memory latency
+// for the window instead of one per element of the loop.  Measured on the
+// 128x128x512 jet: fused kernel 468 -> 464 us (FP32), 322 -> 294 us (BF16);
+// whole step faster in every storage except through the density pass of the
+// equilibrium-referenced forms (3 us slower there, so they keep the loop).
+template <int TY = STY, bool BATCH = false, class T>
 __device__ __forceinline__ void load_window(T* __restrict__ win, const T* __restrict__ f, const KP& k, const Tile& t)
 {
     using TS = TileShape<TY>;
-    for (int w = threadIdx.x; w < TS::W; w += TS::NT) {
-        const int wx = w % TS::WX, r = w / TS::WX;
-        const int wy = r % TS::WY, wz = r / TS::WY;
-        const int x = t.x0 - 1 + wx, y = t.y0 - 1 + wy;
-        if (x <= k.nx && y <= k.ny) win[w] = ldp(f, pidx(k, x, y, t.z - 1 + wz));
+    if constexpr (BATCH) {
+        constexpr int NIT = (TS::W + TS::NT - 1) / TS::NT;
+        T v[NIT];
+        bool ok[NIT];
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int w = (int)threadIdx.x + j * TS::NT;
+            const int wx = w % TS::WX, r = w / TS::WX;
+            const int wy = r % TS::WY, wz = r / TS::WY;
+            const int x = t.x0 - 1 + wx, y = t.y0 - 1 + wy;
+            ok[j] = w < TS::W && x <= k.nx && y <= k.ny;
+            if (ok[j]) v[j] = ldp(f, pidx(k, x, y, t.z - 1 + wz));
+        }
+#pragma unroll
+        for (int j = 0; j < NIT; ++j)
+            if (ok[j]) win[(int)threadIdx.x + j * TS::NT] = v[j];
+    } else {
+        for (int w = threadIdx.x; w < TS::W; w += TS::NT) {
+            const int wx = w % TS::WX, r = w / TS::WX;
+            const int wy = r % TS::WY, wz = r / TS::WY;
+            const int x = t.x0 - 1 + wx, y = t.y0 - 1 + wy;
+            if (x <= k.nx && y <= k.ny) win[w] = ldp(f, pidx(k, x, y, t.z - 1 + wz));
+        }
     }
 }
 
@@ -756,7 +779,7 @@ __global__ __launch_bounds__(DBLOCK) __attribute__((amdgpu_waves_per_eu(kDensity
         if constexpr (kDensityGhosts<S>) store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
         return;
     }
-    load_window<DTY>(win, k.R, k, t);
+    load_window<DTY, !S::kEqRef>(win, k.R, k, t);
     __syncthreads();
     if (!nd.valid) return;
     float d[Q], unused[Q];
@@ -1340,7 +1363,7 @@ k_collide(
     const Tile t = this_tile(k);
     const Node& nd = t.nd;
     if constexpr (kWin) {
-        load_window(win, PD, k, t);
+        load_window<STY, true>(win, PD, k, t);
         __syncthreads();
     }
     if (!nd.valid) return;
