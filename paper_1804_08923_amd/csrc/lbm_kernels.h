@@ -573,9 +573,10 @@ __device__ __forceinline__ int wslot(int lx, int ly, int dx, int dy, int dz)
 // shell of a ragged last tile are skipped: no valid node reads them).
 // BATCH issues all of a lane's loads before its LDS writes: one memory latency
 // for the window instead of one per element of the loop.  Measured on the
-// 128x128x512 jet: fused kernel 468 -> 464 us (FP32), 322 -> 294 us (BF16);
-// whole step faster in every storage except through the density pass of the
-// equilibrium-referenced forms (3 us slower there, so they keep the loop).
+// 128x128x512 jet: fused kernel 468 -> 464 us (FP32), 322 -> 294 us (BF16),
+// adjoint step 1.95 -> 1.73 ms; whole step faster in every storage except
+// through the density pass of the equilibrium-referenced forms (3 us slower
+// there, so they keep the loop).
 template <int TY = STY, bool BATCH = false, class T>
 __device__ __forceinline__ void load_window(T* __restrict__ win, const T* __restrict__ f, const KP& k, const Tile& t)
 {
