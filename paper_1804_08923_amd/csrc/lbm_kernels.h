@@ -541,9 +541,10 @@ __device__ __forceinline__ Tile this_tile(const KP& k)
     Tile t;
     // XCD-aware order: workgroups go round-robin to the 8 XCDs, so a plane's
     // neighbouring tiles would sit on different L2s, each fetching the halo
-    // rows they share.  When the plane's tile count is a multiple of 8, XCD j
-    // takes the contiguous band of tiles [j T/8, (j+1) T/8) of every plane (a
-    // bijection; tile t of planes z and z + 1 stays on one XCD either way).
+    // rows they share.  When the plane's tile count T is a multiple of 8, XCD
+    // j takes the contiguous band of tiles [j T/8, (j+1) T/8) of every plane
+    // (a bijection on the plane's tiles; tile t of planes z and z + 1 still
+    // lands on one XCD, as it does in the plain order for such T).
     uint32_t b = blockIdx.x;
     if ((gridDim.x & 7u) == 0) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
     const int ty = (int)b / k.ntx, tx = (int)b - ty * k.ntx;
@@ -608,15 +609,12 @@ __device__ __forceinline__ void load_window(T* __restrict__ win, const T* __rest
 }
 
 // ---------------------------------------------------------------- density pass
-// fields: PD = (phi, rho - rho_b0) per padded node and XR = the minority
-// colour's fraction, tagged (see "colour fractions"), from the mass sum
-// m0 = rho - rho_b0 and the two colour masses.
 // n / d for the O(1), positive denominators of the fields (a density, a sum
 // of two): the hardware reciprocal refined by two Newton steps and one
 // residual correction, a few FP64 ulps from the rounded quotient, which the
 // callers then round to FP32.  Saves the scaling and fix-up steps of the IEEE
-// division, which this kernel needs no cover for (no zero, denormal or
-// infinite operands).
+// division, which these operands need no cover for (no zero, denormal or
+// infinite values).
 __device__ __forceinline__ double div_fields(double n, double d)
 {
     double r = __builtin_amdgcn_rcp(d);
@@ -626,8 +624,11 @@ __device__ __forceinline__ double div_fields(double n, double d)
     return fma(fma(-d, q, n), r, q);
 }
 
-// phi = (rho_r/rho_r0 - rho_b/rho_b0) / (rho_r/rho_r0 + rho_b/rho_b0) (Eq.
-// order), both quotients scaled by rho_r0 rho_b0: one division
+// fields: PD = (phi, rho - rho_b0) per padded node and XR = the minority
+// colour's fraction, tagged (see "colour fractions"), from the mass sum
+// m0 = rho - rho_b0 and the two colour masses.  phi = (rho_r/rho_r0 -
+// rho_b/rho_b0) / (rho_r/rho_r0 + rho_b/rho_b0) (Eq. order) with both
+// quotients scaled by rho_r0 rho_b0: one division.
 __device__ __forceinline__ float2 store_pd(float2* __restrict__ PD, const KP& k, uint32_t n, double m0, double rr,
                                            double rb)
 {
