@@ -40,10 +40,12 @@ def _periodic_random_problem(nx, ny, nz, **kw):
     return Problem(**base)
 
 
-@pytest.mark.parametrize("shape", [(16, 12, 10), (13, 7, 5), (32, 32, 1)])
+@pytest.mark.parametrize("shape", [(16, 12, 10), (13, 7, 5), (32, 32, 1), (130, 16, 5)])
 def test_single_step_random_state(torch, orc, shape):
     """One step from a random physical state (tau != 1, gamma = 2, eta != 1, g != 0):
-    every population of both colours against the oracle."""
+    every population of both colours against the oracle.  130x16x5 has two
+    x-tiles per row (the second ragged) and 16 resp. 8 tiles per plane in the
+    fused and density passes, so their XCD-banded tile order is in use."""
     prob = _periodic_random_problem(*shape)
     say(f"single step {shape}")
     p, fr, fb, h = random_state(orc, prob, seed=sum(shape))
@@ -237,11 +239,12 @@ def test_small_jet(torch, orc, steps):
     assert np.abs(gb - fb).max() / scale < 1e-5
 
 
-@pytest.mark.parametrize("shape,D", [((3, 3, 3), 2.0), ((130, 5, 4), 3.0)])
+@pytest.mark.parametrize("shape,D", [((3, 3, 3), 2.0), ((130, 5, 4), 3.0), ((130, 16, 6), 5.0)])
 def test_tiny_jets(torch, orc, shape, D):
     """The jet boundaries where almost every node is next to a wall, the inlet
     or the outlet (the 3x3x3 minimum), and on a row two nodes wider than a
-    128-node tile: 30 steps against the oracle."""
+    128-node tile (at 130x16 also with the XCD-banded tile order, 16 resp. 8
+    tiles per plane): 30 steps against the oracle."""
     from paper_1804_08923_amd.workloads import jet_problem
     prob = jet_problem("jet-tiny", *shape, D=D, u=0.04, gamma=2.0, eta=1.0, Re=20.0, We=10.0, Fr=2.0,
                        steps=30, noise_amp=0.01, noise_seed=5)
