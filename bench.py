@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the colour-gradient D3Q27 central-moment LBM step on one MI355X.
 
-Workload: the 128x128x512 liquid-liquid jet (D = 16, u = 0.04, gamma = 2,
-eta = 1, Re = 1e3, We = 50, Fr = 10, 1 % seeded radial inlet noise), synthetic,
-populations resident in HBM.  A step is one full time step of the method
-(density pass + fused collide-perturb-recolour-stream kernel with the jet
-boundaries).  Prints ONE JSON line on stdout; progress goes to stderr.
+Workload: the 256x256x1024 high-Re liquid-liquid jet (67.1 M nodes; D = 24,
+u = 0.05, gamma = 2, eta = 0.01, Re = 1e6, We = 1e3, Fr = 10, 1 % seeded radial
+inlet noise), synthetic, populations resident in HBM.  A step is one full time
+step of the method (density pass + fused collide-perturb-recolour-stream kernel
+with the jet boundaries).  The jet is first developed for `--warmup` steps
+(default 2000, outside the timed region); then `--steps` steps are timed with
+HIP events on the library's stream, with no instrumentation inside the timed
+region.  A separate profiled pass right after it (the library's per-kernel
+events) gives the per-kernel durations.  Prints ONE JSON line on stdout;
+progress goes to stderr.
 
 value = MLUPS of the FP32-storage step (nodes x steps / s / 1e6).
 roofline = the fused kernel's algorithmic bytes per launch / its average
-duration (HIP events recorded by the library around every launch in the timed
-region) against the 8 TB/s HBM peak.
-cpu_baseline = the FP64 oracle on the host cores, on a bounded sample.
+duration in the profiled pass, against the 8 TB/s HBM peak.
+cpu_baseline = the FP64 oracle on the host cores, on a bounded slab sample of
+the same jet, on all threads and on one.
 """
 from __future__ import annotations
 
@@ -41,56 +46,62 @@ DENSITY_BYTES = {"fp32": 27 * 4 + 16 + 12, "bf16": 27 * 2 + 16 + 12, "fp16": 27 
                  "bf16eq": 28 * 2 + 16 + 16 + 12, "fp16eq": 28 * 2 + 16 + 16 + 12}
 PAPER_CONTEXT = {"mlups": [1.2, 12.0], "hardware": "unspecified cluster (COMA / Earth Simulator named)",
                  "workload": "240x240x1200 UT jet, 20000 iterations in ~32 h"}
+PROFILE_STEPS = 50
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(storage):
+def measured_traffic(storage, workload):
     """HBM bytes per fused-kernel launch from committed rocprofv3 counter runs,
-    used only while the kernel source is unchanged since they were taken."""
+    used only while the kernel source is unchanged since they were taken and
+    only for the workload they were taken on."""
     from paper_1804_08923_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    ent = t.get(storage)
+    ent = t.get(f"{workload}/{storage}")
     if not ent or ent.get("kernel_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
 
 
-def run_leg(prob, steps, warmup, diagnostics=False):
+def _advance(sim, n, chunk=100):
+    done = 0
+    while done < n:
+        k = min(chunk, n - done)
+        sim.step(k)
+        done += k
+
+
+def run_leg(prob, steps, warmup, diagnostics=False, keep=False):
+    """Develop the jet for `warmup` steps, time `steps` steps (no
+    instrumentation), then profile PROFILE_STEPS more steps per kernel."""
     import torch
 
     from paper_1804_08923_amd.lbm import LBM
     sim = LBM(prob, device="cuda:0")
     N = prob.n_nodes
-    sim.profile(True)
-    done = 0
-    while done < warmup:
-        k = min(50, warmup - done)
-        sim.step(k)
-        done += k
+    t_dev = time.perf_counter()
+    _advance(sim, warmup)
     torch.cuda.synchronize()
-    sim.profile_read()
-    torch.cuda.synchronize()
+    dev_s = time.perf_counter() - t_dev
+    stream = sim.stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    e0.record()
-    done = 0
-    while done < steps:
-        k = min(100, steps - done)
-        sim.step(k)
-        done += k
-    e1.record()
+    e0.record(stream)
+    _advance(sim, steps)
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    # profiled pass: the library records events around its kernel groups
+    sim.profile(True)
+    _advance(sim, PROFILE_STEPS)
     kms, launches = sim.profile_read()
-    bnd = kms[2] / launches[2]
     sim.profile(False)
     m = sim.macroscopic(audit=True)
     audit = m["audit"]
@@ -98,71 +109,99 @@ def run_leg(prob, steps, warmup, diagnostics=False):
     finite = bool(torch.isfinite(m["u"]).all().item())
     del m
     diag = None
-    if diagnostics:
-        # jet diagnostics (leading edge, fragments) of the final state, timed
-        # on the host clock around the synchronising call
+    if diagnostics and prob.bc == "jet":
         sim.jet_diagnostics()
-        reps = 5
+        reps = 3
         t1 = time.perf_counter()
         for _ in range(reps):
             stats, vol = sim.jet_diagnostics()
-        diag = dict(ms=round((time.perf_counter() - t1) / reps * 1e3, 3), step=warmup + steps, **stats)
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
+        diag = dict(ms=round((time.perf_counter() - t1) / reps * 1e3, 3), step=sim.time, **stats)
+    if not keep:
+        sim.close()
+        del sim
+        sim = None
+        torch.cuda.empty_cache()
     st = prob.storage
     mlups = N * steps / (ms * 1e-3) / 1e6
     avg_fused = kms[1] / launches[1]
     avg_dens = kms[0] / launches[0]
     achieved = FUSED_BYTES[st] * N / (avg_fused * 1e-3) / 1e9
-    return dict(mlups=mlups, ms_per_step=ms / steps, wall_s=wall, umax=umax, finite=finite, audit=audit, diag=diag,
-                fused_ms=avg_fused, density_ms=avg_dens, boundary_ms=bnd, fused_gbs=achieved,
-                step_roofline_frac=mlups / (HBM_PEAK_GBS * 1e9 / STEP_BYTES[st] / 1e6))
+    return dict(mlups=mlups, ms_per_step=ms / steps, wall_s=wall, develop_s=dev_s, umax=umax, finite=finite,
+                audit=audit, diag=diag, fused_ms=avg_fused, density_ms=avg_dens, boundary_ms=kms[2] / launches[2],
+                profiled_step_ms=sum(kms) / launches[1], fused_gbs=achieved,
+                step_roofline_frac=mlups / (HBM_PEAK_GBS * 1e9 / STEP_BYTES[st] / 1e6), sim=sim)
 
 
-def adjoint_leg(prob, nadj=10):
-    """Cost of one adjoint step (lbm_adjoint_step) at a developed state, and of
-    recomputing one forward state from a checkpoint (set_state + step +
-    get_state), both timed with events on the library's stream."""
+def adjoint_leg(prob, fwd_ms, nadj=10):
+    """Cost of one reverse step at a developed state: the adjoint step
+    (lbm_adjoint_step) and the recompute of the forward state it needs from the
+    previous one (a forward step into a caller-held snapshot), both timed with
+    events on the library's stream; their sum with the forward step is the
+    full cost of one step of a checkpointed gradient."""
     import torch
 
     from paper_1804_08923_amd.lbm import LBM
     sim = LBM(prob, device="cuda:0", adjoint=True)
-    sim.step(50)
-    st = sim.get_state()
+    _advance(sim, 50)
+    snap = [sim.new_snapshot(), sim.new_snapshot()]
+    sim.save_snapshot(snap[0])
     t = sim.time
     g = torch.Generator(device="cuda:0")
     g.manual_seed(5)
-    lam = [torch.randn(st.shape, generator=g, device="cuda:0", dtype=torch.float32), torch.empty_like(st)]
+    lam = [torch.randn((2 * 27, prob.n_nodes), generator=g, device="cuda:0", dtype=torch.float32), None]
+    lam[1] = torch.empty_like(lam[0])
     dA = torch.zeros(1, dtype=torch.float64, device="cuda:0")
     du = torch.zeros(prob.nx * prob.ny, dtype=torch.float32, device="cuda:0")
+    stream = sim.stream
     for i in range(2):
-        sim.adjoint_step(st, t, lam[i % 2], lam[1 - i % 2], dA, du)
+        sim.adjoint_step_snapshot(snap[0], t, lam[i % 2], lam[1 - i % 2], dA, du)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(stream)
     for i in range(nadj):
-        sim.adjoint_step(st, t, lam[i % 2], lam[1 - i % 2], dA, du)
-    e1.record()
+        sim.adjoint_step_snapshot(snap[0], t, lam[i % 2], lam[1 - i % 2], dA, du)
+    e1.record(stream)
     torch.cuda.synchronize()
     adj_ms = e0.elapsed_time(e1) / nadj
     finite = bool(torch.isfinite(lam[nadj % 2]).all().item()) and bool(torch.isfinite(dA).all().item())
-    e0.record()
-    for _ in range(nadj):
-        sim.set_state(st, t)
-        sim.step(1)
-        sim.get_state()
-    e1.record()
+    # recompute: restore the checkpointed state once, then step into snapshots
+    sim.load_snapshot(snap[0], t)
+    sim.step_to_snapshot(snap[1])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(nadj):
+        sim.step_to_snapshot(snap[i % 2])
+    e1.record(stream)
     torch.cuda.synchronize()
     rec_ms = e0.elapsed_time(e1) / nadj
+    e0.record(stream)
+    for _ in range(nadj):
+        sim.load_snapshot(snap[0], t)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    load_ms = e0.elapsed_time(e1) / nadj
     sim.close()
-    del sim, st, lam
+    del sim, snap, lam
     torch.cuda.empty_cache()
-    return dict(adjoint_ms=adj_ms, recompute_ms=rec_ms, finite=finite)
+    return dict(adjoint_ms=adj_ms, recompute_ms=rec_ms, load_ms=load_ms, finite=finite,
+                gradient_step_ms=fwd_ms + rec_ms + adj_ms)
 
 
-def cpu_baseline(prob, nz_sample=64, steps=32):
-    """The FP64 oracle on a slab of the same jet (full cross-section, nz_sample planes)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, nz_sample=8, budget_s=10.0):
+    """The FP64 oracle on a slab of the same jet (full cross-section, nz_sample
+    planes, from the initial state), on all threads and on one, each for about
+    budget_s seconds."""
     from oracle import Oracle
     from oracle import make_params as or_params
     import numpy as np
@@ -170,23 +209,37 @@ def cpu_baseline(prob, nz_sample=64, steps=32):
     orc = Oracle("f64")
     p = or_params(sp)
     N = sp.n_nodes
-    fr, fb, h = orc.init_fields(p, np.zeros(N), np.full(N, sp.rho_b0))
-    t0 = time.perf_counter()
-    orc.step(p, sp.A, fr, fb, h, 0, steps)
-    dt = time.perf_counter() - t0
-    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{sp.nx}x{sp.ny}x{sp.nz} slab of the jet (same inlet, walls, outlet), {steps} steps "
-                      f"from the initial state, FP64, {dt:.1f} s"}
+    res = {}
+    n_all = orc.num_threads()
+    for label, threads in (("all", n_all), ("one", 1)):
+        orc.set_num_threads(threads)
+        fr, fb, h = orc.init_fields(p, np.zeros(N), np.full(N, sp.rho_b0))
+        steps, t_used = 0, 0.0
+        while t_used < budget_s:
+            t0 = time.perf_counter()
+            orc.step(p, sp.A, fr, fb, h, steps, 1)
+            t_used += time.perf_counter() - t0
+            steps += 1
+        res[label] = (N * steps / t_used / 1e6, steps, t_used, threads)
+        del fr, fb, h
+    orc.set_num_threads(n_all)
+    v, s, t, c = res["all"]
+    v1, s1, t1, _ = res["one"]
+    return {"value": round(v, 4), "unit": "MLUPS", "cores": c, "kind": "oracle",
+            "sample": f"{sp.nx}x{sp.ny}x{sp.nz} slab of the jet (same inlet, walls, outlet), FP64, from the initial "
+                      f"state: {s} steps in {t:.1f} s on {c} threads; {s1} steps in {t1:.1f} s on 1 thread",
+            "single_core_mlups": round(v1, 4), "cpu_model": _cpu_model()}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="jet-128x128x512")
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--workload", default="jet-256x256x1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the BF16/FP16 storage legs")
+    ap.add_argument("--legs", default="bf16,fp16,bf16eq,fp16eq", help="storage legs to run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-step timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (calibrates hardware byte counters)")
@@ -201,7 +254,7 @@ def main():
     from paper_1804_08923_amd.workloads import WORKLOADS
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     prob = WORKLOADS[args.workload]().replace(storage="fp32")
-    log(f"bench: {prob.name} ({prob.n_nodes} nodes) fp32, warmup {args.warmup}, steps {args.steps}")
+    log(f"bench: {prob.name} ({prob.n_nodes} nodes) fp32, develop {args.warmup} steps, time {args.steps} steps")
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -215,36 +268,43 @@ def main():
         log("bench: copy probe (1 GiB read + 1 GiB write) done")
 
     main_leg = run_leg(prob, args.steps, args.warmup, diagnostics=True)
-    log(f"bench: fp32 {main_leg['mlups']:.0f} MLUPS, fused kernel {main_leg['fused_ms']:.3f} ms "
-        f"({main_leg['fused_gbs']:.0f} GB/s), density {main_leg['density_ms']:.3f} ms, "
+    log(f"bench: fp32 {main_leg['mlups']:.0f} MLUPS ({main_leg['ms_per_step']:.3f} ms/step); profiled: fused "
+        f"{main_leg['fused_ms']:.3f} ms ({main_leg['fused_gbs']:.0f} GB/s), density {main_leg['density_ms']:.3f} ms, "
         f"boundary {main_leg['boundary_ms']:.3f} ms")
-    log(f"bench: jet diagnostics {main_leg['diag']}")
+    log(f"bench: jet after {main_leg['diag']['step'] if main_leg['diag'] else '?'} steps: {main_leg['diag']}")
     legs = {}
     if not args.no_legs:
-        for st in ("bf16", "fp16", "bf16eq", "fp16eq"):
+        for st in [s for s in args.legs.split(",") if s]:
             r = run_leg(prob.replace(storage=st), args.steps, args.warmup)
             legs[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                         "x_fp32": round(r["mlups"] / main_leg["mlups"], 3),
                         "step_roofline_frac": round(r["step_roofline_frac"], 4),
                         "fused_kernel_ms": round(r["fused_ms"], 4), "fused_kernel_gbs": round(r["fused_gbs"], 1),
-                        "finite": r["finite"]}
-            log(f"bench: {st} {r['mlups']:.0f} MLUPS ({r['mlups'] / main_leg['mlups']:.2f}x fp32)")
+                        "density_kernel_ms": round(r["density_ms"], 4), "finite": r["finite"]}
+            log(f"bench: {st} {r['mlups']:.0f} MLUPS ({r['mlups'] / main_leg['mlups']:.2f}x fp32), fused "
+                f"{r['fused_ms']:.3f} ms, density {r['density_ms']:.3f} ms")
     adj = None
     if not args.no_adjoint:
-        a = adjoint_leg(prob)
-        adj = {"adjoint_step_ms": round(a["adjoint_ms"], 4), "forward_step_ms": round(main_leg["ms_per_step"], 4),
-               "ratio": round(a["adjoint_ms"] / main_leg["ms_per_step"], 3),
-               "recompute_step_ms": round(a["recompute_ms"], 4), "finite": a["finite"],
-               "note": "adjoint step alone; recompute = set_state + step + get_state of one checkpointed state"}
-        log(f"bench: adjoint step {a['adjoint_ms']:.3f} ms = {adj['ratio']:.2f}x forward, "
-            f"recompute {a['recompute_ms']:.3f} ms")
+        a = adjoint_leg(prob, main_leg["ms_per_step"])
+        fwd = main_leg["ms_per_step"]
+        adj = {"adjoint_step_ms": round(a["adjoint_ms"], 4), "forward_step_ms": round(fwd, 4),
+               "ratio": round(a["adjoint_ms"] / fwd, 3),
+               "recompute_step_ms": round(a["recompute_ms"], 4), "recompute_ratio": round(a["recompute_ms"] / fwd, 3),
+               "checkpoint_load_ms": round(a["load_ms"], 4),
+               "gradient_step_ms": round(a["gradient_step_ms"], 4),
+               "gradient_step_ratio": round(a["gradient_step_ms"] / fwd, 3), "finite": a["finite"],
+               "note": "per step of a checkpointed gradient: forward step + recompute (a step into a snapshot) + "
+                       "adjoint step; the checkpoint load is paid once per segment"}
+        log(f"bench: adjoint step {a['adjoint_ms']:.3f} ms = {adj['ratio']:.2f}x forward, recompute "
+            f"{a['recompute_ms']:.3f} ms = {adj['recompute_ratio']:.2f}x, gradient step {adj['gradient_step_ratio']:.2f}x")
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
         cpu = cpu_baseline(prob)
-        log(f"bench: oracle {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+        log(f"bench: oracle {cpu['value']:.3f} MLUPS on {cpu['cores']} threads, {cpu['single_core_mlups']:.4f} on one "
+            f"({cpu['cpu_model']})")
 
-    traffic = measured_traffic("fp32")
+    traffic = measured_traffic("fp32", prob.name)
     line = {
         "metric": "MLUPS and % HBM roofline: FP32 vs BF16-storage fused step; adjoint/forward cost",
         "value": round(main_leg["mlups"], 1),
@@ -259,12 +319,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": prob.name, "nodes": prob.n_nodes, "lattice": "D3Q27 two-colour",
-                   "storage": "fp32", "bc": prob.bc, "gamma": prob.gamma, "Re": prob.meta.get("Re"),
-                   "We": prob.meta.get("We"), "Fr": prob.meta.get("Fr")},
+                   "storage": "fp32", "bc": prob.bc, "gamma": prob.gamma, "eta": prob.meta.get("eta"),
+                   "Re": prob.meta.get("Re"), "We": prob.meta.get("We"), "Fr": prob.meta.get("Fr"),
+                   "developed_steps": args.warmup},
         "roofline": {"bound": "hbm", "achieved": round(main_leg["fused_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(main_leg["fused_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_collide<jet, fp32> (fused collide-recolour-stream)",
-                     "bytes_per_node": FUSED_BYTES["fp32"], "avg_launch_ms": round(main_leg["fused_ms"], 4)},
+                     "bytes_per_node": FUSED_BYTES["fp32"], "avg_launch_ms": round(main_leg["fused_ms"], 4),
+                     "timing": f"library events around each launch, {PROFILE_STEPS} steps right after the timed region"},
         "step_roofline_frac": round(main_leg["step_roofline_frac"], 4),
         "step_bytes_per_node": STEP_BYTES["fp32"],
         "impl_bytes_per_node": FUSED_BYTES["fp32"] + DENSITY_BYTES["fp32"],

@@ -72,7 +72,7 @@ enum lbm_init_kind {
 /* Problem parameters in lattice units (c = delta_x = delta_t = 1). */
 typedef struct lbm_params {
     int32_t nx, ny, nz;   /* lattice size; periodic: >= 1 each; jet: >= 3 each; each <= 65535;
-                             (nx+2)(ny+2)(nz+2) < 2^28 */
+                             (nx+2)(ny+2)(nz+2) <= 2^29 padded nodes */
     int32_t bc;           /* enum lbm_bc */
     int32_t storage;      /* enum lbm_storage: population storage format */
     int32_t init;         /* enum lbm_init_kind used by lbm_init */
@@ -105,6 +105,11 @@ typedef struct lbm_sizes {
     uint64_t inlet_bytes;   /* optional inlet axial-velocity profile, nx*ny floats */
     uint64_t adjoint_bytes; /* adjoint work buffer (see lbm_adjoint_step) */
     uint64_t state_bytes;   /* a full FP32 state: 54 floats per node (fr[27], fb[27]) */
+    uint64_t snap_bytes;    /* one state snapshot in the library's own layout (see lbm_step_into):
+                               27 population planes of (nx+2)(ny+2)(nz+2) padded nodes in the
+                               storage format (28 for BF16_EQ / FP16_EQ), a 16-byte record per
+                               padded node (two for BF16_EQ / FP16_EQ), and for the jet one
+                               outlet plane of 54 floats per (x, y): about 124 B per node in FP32 */
 } lbm_sizes;
 
 /* Device buffers owned by the caller; must stay valid until lbm_destroy(). */
@@ -160,8 +165,35 @@ int lbm_get_state(lbm_handle* h, float* state);
 int lbm_set_state(lbm_handle* h, const float* state, int64_t t);
 
 /* Time level of the current state (number of steps since init or the t of
- * the last lbm_set_state). */
+ * the last lbm_set_state / lbm_snapshot_load). */
 int64_t lbm_time(const lbm_handle* h);
+
+/* State snapshots: the state between two steps in the library's own layout
+ * (the colour-blind deviations as the last step streamed them, the per-node
+ * recolouring records that rebuild both colours, Eqs. op3r/op3b, and the
+ * jet's outlet plane of Sec. IV A), for checkpointing a run whose gradient
+ * is taken with lbm_adjoint_step_snapshot.  A snapshot is snap_bytes of
+ * caller-owned device memory, 256-byte aligned; the library keeps no pointer
+ * to it except as stated for lbm_step_into.  A snapshot is only meaningful
+ * for the handle (parameters and storage) that wrote it.
+ *
+ * lbm_step_into: one full time step (as lbm_step) whose result is written
+ *   into snap instead of the handle's own buffers; snap then IS the current
+ *   state (time + 1) and is read in place by the next call that reads the
+ *   state (lbm_step, lbm_macroscopic, lbm_get_state, lbm_snapshot_save, ...),
+ *   so it must stay valid and unmodified until the next lbm_step,
+ *   lbm_step_into, lbm_set_state or lbm_snapshot_load.  snap must not be the
+ *   current state itself (LBM_ERR_INVALID_ARG).  This is the recompute of a
+ *   checkpointed segment at the cost of a forward step.
+ * lbm_snapshot_save: copy the current state into snap (device copies on the
+ *   stream).  LBM_ERR_STATE right after lbm_init or lbm_set_state, whose
+ *   general state has no snapshot form (take one step first, or keep the
+ *   lbm_get_state array).
+ * lbm_snapshot_load: make a copy of snap the current state, at time level t
+ *   (the inlet noise depends on it); the handle's own buffers receive it. */
+int lbm_step_into(lbm_handle* h, void* snap);
+int lbm_snapshot_save(lbm_handle* h, void* snap);
+int lbm_snapshot_load(lbm_handle* h, const void* snap, int64_t t);
 
 /* One reverse (adjoint) step of the time step t -> t+1 (not in the paper:
  * the hand-written reverse mode of every operation listed at the top of
@@ -185,6 +217,15 @@ int64_t lbm_time(const lbm_handle* h);
  * of the handle unchanged.  Enqueued on the handle's stream; no host sync. */
 int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float* lambda_in,
                      float* lambda_out, double* dJ_dA, float* dJ_du_in);
+
+/* The same reverse step with the forward state x_t given as a snapshot
+ * (device, snap_bytes, written by lbm_step_into or lbm_snapshot_save of this
+ * handle at time level t) instead of the 54-plane FP32 array.  Arguments,
+ * outputs and error behaviour as lbm_adjoint_step; lambda_out must not
+ * alias lambda_in or snap_t.  The forward quantities are rebuilt from the
+ * snapshot exactly as the next lbm_step would read it. */
+int lbm_adjoint_step_snapshot(lbm_handle* h, const void* snap_t, int64_t t, const float* lambda_in,
+                              float* lambda_out, double* dJ_dA, float* dJ_du_in);
 
 /* Instrumentation: with enable != 0, lbm_step records HIP events on its
  * stream around its kernel groups (density pass; fused collide-recolour-

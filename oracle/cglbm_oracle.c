@@ -583,6 +583,16 @@ int or_num_threads(void)
 #endif
 }
 
+/* thread count of the parallel loops that follow (n >= 1) */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int or_step(const or_params* p, const or_real* A, const or_real* inlet_uz, or_real* fr,
             or_real* fb, or_real* hist, int64_t t0, int32_t nsteps)
 {

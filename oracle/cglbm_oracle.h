@@ -95,6 +95,7 @@ void or_macroscopic(const or_params* p, const or_real* fr, const or_real* fb,
                     or_real* rho_r, or_real* rho_b, or_real* u /* 3N */, or_real* phi);
 double or_noise(uint64_t seed, int64_t t, int32_t x, int32_t y, int32_t nx, int32_t ny);
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

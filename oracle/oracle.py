@@ -127,6 +127,7 @@ class Oracle:
         L.or_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.or_noise.restype = C.c_double
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
 
     # scalar argument type of this variant (complex is passed as a 2-double struct)
     def _scalar_t(self):
@@ -271,3 +272,6 @@ class Oracle:
 
     def num_threads(self) -> int:
         return self.lib.or_num_threads()
+
+    def set_num_threads(self, n: int) -> None:
+        self.lib.or_set_num_threads(int(n))

@@ -3,14 +3,18 @@
 ``rollout(sim, x0, nsteps, every=K, A=..., u_in=...)`` returns the state after
 ``nsteps`` steps of ``sim`` (an ``LBM`` created with ``adjoint=True``) started
 from ``x0`` (lbm_get_state layout) as a differentiable torch tensor.  Its
-backward pass runs ``lbm_adjoint_step`` backwards in time and yields the
+backward pass runs the library's adjoint step backwards in time and yields the
 gradients with respect to ``x0``, the perturbation strength ``A`` and the
 inlet axial-velocity profile ``u_in``.
 
-Checkpointing: the forward pass keeps the state every ``every`` steps; the
-backward pass recomputes the states of one segment at a time from its
-checkpoint (lbm_set_state, lbm_step, lbm_get_state) and reverses the segment.
-Memory: (nsteps/every + every) states.  All arithmetic runs in the library.
+Checkpointing: the forward pass writes the state that ends every K-step
+segment straight into a snapshot (lbm_step_into: the library's own layout,
+no conversion).  The backward pass takes one segment at a time: it loads the
+segment's checkpoint, recomputes the segment's states by stepping into
+snapshot buffers (one forward step each), and reverses the segment with
+lbm_adjoint_step_snapshot (lbm_adjoint_step for x0 itself).  Memory:
+nsteps/K checkpoints plus K - 1 segment snapshots of snap_bytes each.  All
+arithmetic runs in the library.
 """
 from __future__ import annotations
 
@@ -25,9 +29,12 @@ class _Rollout(torch.autograd.Function):
         sim.set_state(x0, t0)
         ckpts = [x0.detach().clone().contiguous()]
         for s in range(nsteps):
-            sim.step(1)
             if (s + 1) % every == 0 and s + 1 < nsteps:
-                ckpts.append(sim.get_state())
+                snap = sim.new_snapshot()
+                sim.step_to_snapshot(snap)
+                ckpts.append(snap)
+            else:
+                sim.step(1)
         xT = sim.get_state()
         ctx.sim, ctx.t0, ctx.nsteps, ctx.every, ctx.ckpts = sim, t0, nsteps, every, ckpts
         ctx.has_u = u_in is not None
@@ -43,18 +50,26 @@ class _Rollout(torch.autograd.Function):
         dA = torch.zeros(1, dtype=torch.float64, device=dev)
         du = torch.zeros(sim.prob.nx * sim.prob.ny, dtype=torch.float32, device=dev) if ctx.has_u else None
         K, n, t0 = ctx.every, ctx.nsteps, ctx.t0
+        seg_snaps = [sim.new_snapshot() for _ in range(min(K, n) - 1)]
         for seg in reversed(range(len(ctx.ckpts))):
             s0 = seg * K
             s1 = min(n, s0 + K)
-            states = [ctx.ckpts[seg]]
-            sim.set_state(states[0], t0 + s0)
-            for _ in range(s0 + 1, s1):
-                sim.step(1)
-                states.append(sim.get_state())
+            ck = ctx.ckpts[seg]
+            if seg == 0:
+                sim.set_state(ck, t0)
+            else:
+                sim.load_snapshot(ck, t0 + s0)
+            for j in range(s1 - s0 - 1):
+                sim.step_to_snapshot(seg_snaps[j])  # the state at t0 + s0 + 1 + j
             for s in reversed(range(s0, s1)):
-                sim.adjoint_step(states[s - s0], t0 + s, lam, lam_out, dA, du)
+                if s > s0:
+                    sim.adjoint_step_snapshot(seg_snaps[s - s0 - 1], t0 + s, lam, lam_out, dA, du)
+                elif seg == 0:
+                    sim.adjoint_step(ck, t0 + s, lam, lam_out, dA, du)
+                else:
+                    sim.adjoint_step_snapshot(ck, t0 + s, lam, lam_out, dA, du)
                 lam, lam_out = lam_out, lam
-            del states
+        del seg_snaps
         ctx.ckpts = None
         if du is not None:
             du = du.reshape(ctx.u_shape)

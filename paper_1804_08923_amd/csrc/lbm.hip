@@ -14,17 +14,25 @@
 
 using namespace cglbm;
 
+// One complete state: population planes (shifted form, or the general form
+// of 54 planes), the recolouring records R, the reference records of the
+// referenced 16-bit forms, and (jet) the outlet plane the next step's
+// convective condition starts from.
+struct StateSet {
+    void* pop;
+    float4* R;
+    uint4* Q;
+    float* hist;
+};
+
 struct lbm_handle {
     lbm_params p;
     KP k;
-    void* pop[2];
-    int cur;            // population buffer holding the current state
-    float4* R[2];       // (tagged minority fraction, V) written together with pop[0] resp. pop[1]
-    uint4* Qr[2];       // referenced 16-bit storage: reference records written with pop[0] resp. pop[1]
+    StateSet own[2];    // the handle's A and B sets (caller buffers given to lbm_init)
+    StateSet ext;       // a caller snapshot that lbm_step_into made current
+    int cs;             // current set: 0 or 1 (own), 2 (ext)
     float2* PD;         // (phi, rho - rho_b0) per padded node
     float* XR;          // rho_r / rho per padded node
-    float* hist[2];     // outlet plane (jet): [hprev] previous step, [hprev ^ 1] current
-    int hprev;
     double* audit;
     void* adjoint;
     hipStream_t stream;
@@ -107,8 +115,19 @@ int validate(const lbm_params* p)
     if (!(p->grad_eps >= 0)) return fail(LBM_ERR_INVALID_ARG, "grad_eps must be >= 0");
     if (p->init < LBM_INIT_FIELDS || p->init > LBM_INIT_JET) return fail(LBM_ERR_INVALID_ARG, "unknown init %d", p->init);
     if (p->bc == LBM_BC_JET) {
-        if (!(p->inlet_D >= 0) || !std::isfinite(p->inlet_u) || !(p->noise_amp >= 0))
+        if (!(p->inlet_D >= 0) || !std::isfinite(p->inlet_u) || !(p->noise_amp >= 0) ||
+            !std::isfinite(p->inlet_cx) || !std::isfinite(p->inlet_cy) || !std::isfinite(p->inlet_D))
             return fail(LBM_ERR_INVALID_ARG, "bad inlet parameters");
+        // the inlet circle must not reach the outermost rows and columns
+        const double r = 0.5 * p->inlet_D;
+        const int x0 = std::max(0, (int)std::floor(p->inlet_cx - r)), x1 = std::min(p->nx - 1, (int)std::ceil(p->inlet_cx + r));
+        const int y0 = std::max(0, (int)std::floor(p->inlet_cy - r)), y1 = std::min(p->ny - 1, (int)std::ceil(p->inlet_cy + r));
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const double dx = x - p->inlet_cx, dy = y - p->inlet_cy;
+                if (dx * dx + dy * dy < r * r && (x == 0 || y == 0 || x == p->nx - 1 || y == p->ny - 1))
+                    return fail(LBM_ERR_INVALID_ARG, "the inlet circle touches a side wall at (%d, %d)", x, y);
+            }
     }
     if (p->init == LBM_INIT_DROPLET && !(p->drop_W > 0))
         return fail(LBM_ERR_INVALID_ARG, "droplet interface width must be > 0");
@@ -158,6 +177,7 @@ void fill_kp(const lbm_params* p, const float* inlet, KP* k)
     k->seed = p->noise_seed;
     k->t = 0;
     k->unshifted = 1;
+    k->xr_tagged = 0;
     k->inlet_uz = inlet;
     k->R = nullptr;
 }
@@ -188,15 +208,65 @@ int dispatch(int bc, int storage, F&& f)
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 // parameters for reading the current state
+const StateSet& cur_set(const lbm_handle* h) { return h->cs == 2 ? h->ext : h->own[h->cs]; }
+
+// the own set a step may write: the one not holding the current state
+int free_own(const lbm_handle* h) { return h->cs == 0 ? 1 : 0; }
+
+// parameters for reading the current state
 KP read_kp(const lbm_handle* h)
 {
+    const StateSet& c = cur_set(h);
     KP k = h->k;
     k.t = h->t;
     k.unshifted = h->unshifted;
-    k.R = h->R[h->cur];
-    k.Qrec = h->Qr[h->cur];
+    k.R = c.R;
+    k.Qrec = c.Q;
     k.z0 = 0;
     return k;
+}
+
+// Layout of a state snapshot (a shifted state, as a step leaves it): the
+// population planes 0..26 (0..27 in the referenced 16-bit forms, whose rest
+// population also uses plane 27) with the plane stride of the population
+// buffers, the recolouring records R, the reference records (referenced
+// forms), and the jet's outlet plane (54 floats per (x, y)); each part
+// 256-byte aligned.  Returns the byte count; with base != NULL fills *s.
+uint64_t snap_layout(const lbm_params* p, char* base, StateSet* s)
+{
+    const uint64_t NP = padded_nodes(p), plane = (uint64_t)p->nx * p->ny;
+    const uint64_t planes = eq_ref(p->storage) ? Q + 1 : Q;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        char* q = base ? base + off : nullptr;
+        off += align256(bytes);
+        return q;
+    };
+    char* pop = take(planes * NP * elem_bytes(p->storage));
+    char* R = take(NP * 16);
+    char* Qr = eq_ref(p->storage) ? take(NP * 16) : nullptr;
+    char* hist = p->bc == LBM_BC_JET ? take(2ull * Q * plane * sizeof(float)) : nullptr;
+    if (s) {
+        s->pop = pop;
+        s->R = (float4*)R;
+        s->Q = (uint4*)Qr;
+        s->hist = (float*)hist;
+    }
+    return off;
+}
+
+// bytes of the parts of a shifted state (what a snapshot holds)
+struct SnapBytes {
+    size_t pop, rec, hist;
+};
+SnapBytes snap_bytes_of(const lbm_params* p)
+{
+    const uint64_t NP = padded_nodes(p), plane = (uint64_t)p->nx * p->ny;
+    SnapBytes b;
+    b.pop = (size_t)((eq_ref(p->storage) ? Q + 1 : Q) * NP * elem_bytes(p->storage));
+    b.rec = (size_t)(NP * 16);
+    b.hist = p->bc == LBM_BC_JET ? (size_t)(2ull * Q * plane * sizeof(float)) : 0;
+    return b;
 }
 
 }  // namespace
@@ -220,6 +290,7 @@ int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
     out->inlet_bytes = plane * sizeof(float);
     out->adjoint_bytes = adjoint_layout(NP, N, plane, nblk, nullptr, nullptr);
     out->state_bytes = 2ull * Q * N * sizeof(float);
+    out->snap_bytes = snap_layout(p, nullptr, nullptr);
     return LBM_OK;
 }
 
@@ -245,20 +316,20 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->p = *p;
     fill_kp(p, buf->inlet_uz, &H->k);
     const size_t NP = H->k.NP;
-    H->pop[0] = buf->pop_a;
-    H->pop[1] = buf->pop_b;
-    H->cur = 0;
-    H->R[0] = (float4*)buf->fields;
-    H->R[1] = (float4*)(buf->fields + 4 * NP);
+    H->own[0].pop = buf->pop_a;
+    H->own[1].pop = buf->pop_b;
+    H->cs = 0;
+    H->ext = StateSet{nullptr, nullptr, nullptr, nullptr};
+    H->own[0].R = (float4*)buf->fields;
+    H->own[1].R = (float4*)(buf->fields + 4 * NP);
     const size_t qf = eq_ref(p->storage) ? 8 * NP : 0;  // records after R, 16-byte aligned
-    H->Qr[0] = eq_ref(p->storage) ? (uint4*)(buf->fields + 8 * NP) : nullptr;
-    H->Qr[1] = eq_ref(p->storage) ? (uint4*)(buf->fields + 12 * NP) : nullptr;
+    H->own[0].Q = eq_ref(p->storage) ? (uint4*)(buf->fields + 8 * NP) : nullptr;
+    H->own[1].Q = eq_ref(p->storage) ? (uint4*)(buf->fields + 12 * NP) : nullptr;
     H->PD = (float2*)(buf->fields + 8 * NP + qf);
     H->XR = buf->fields + 10 * NP + qf;
     const size_t hplane = 2 * (size_t)Q * H->k.plane;
-    H->hist[0] = p->bc == LBM_BC_JET ? buf->hist : nullptr;
-    H->hist[1] = p->bc == LBM_BC_JET ? buf->hist + hplane : nullptr;
-    H->hprev = 0;
+    H->own[0].hist = p->bc == LBM_BC_JET ? buf->hist : nullptr;
+    H->own[1].hist = p->bc == LBM_BC_JET ? buf->hist + hplane : nullptr;
     H->audit = buf->audit;
     H->adjoint = buf->adjoint;
     H->stream = (hipStream_t)hip_stream;
@@ -277,7 +348,7 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
         using S = decltype(st);
         (void)bc;
         const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
-        hipLaunchKernelGGL(k_init<S>, H->grid_all, dim3(BLOCK), 0, H->stream, (typename S::T*)H->pop[0], H->R[0], H->k,
+        hipLaunchKernelGGL(k_init<S>, H->grid_all, dim3(BLOCK), 0, H->stream, (typename S::T*)H->own[0].pop, H->own[0].R, H->k,
                            p->init, rho_r, rho_b, u, p->drop_cx, p->drop_cy, p->drop_cz, p->drop_R, p->drop_W,
                            p->rho_r0, p->rho_b0, ar, p->alpha_b, (double)H->k.rho_b0);
         LAUNCH_CHECK();
@@ -291,69 +362,148 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     return LBM_OK;
 }
 
-int lbm_step(lbm_handle* h, int32_t n_steps)
+}  // extern "C"
+
+namespace {
+
+// One full time step from the current state into the state set dst, which
+// becomes the current state.
+int step_once(lbm_handle* h, const StateSet& dst_set, int dst_cs)
 {
-    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
-    if (n_steps < 0) return fail(LBM_ERR_INVALID_ARG, "n_steps < 0");
     return dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         using T = typename S::T;
         constexpr int BC = decltype(bc)::value;
         constexpr bool jet = BC == LBM_BC_JET;
-        for (int s = 0; s < n_steps; ++s) {
-            KP k = read_kp(h);
-            const T* src = (const T*)h->pop[h->cur];
-            T* dst = (T*)h->pop[h->cur ^ 1];
-            float4* Rout = h->R[h->cur ^ 1];
-            uint4* Qout = h->Qr[h->cur ^ 1];
-            float* hprev = h->hist[h->hprev];
-            float* hcur = h->hist[h->hprev ^ 1];
-            hipEvent_t* e = nullptr;
-            if (h->profiling) {
-                while (h->ev.size() < h->ev_used + 5) {
-                    hipEvent_t x;
-                    HIP_CHECK(hipEventCreate(&x));
-                    h->ev.push_back(x);
-                }
-                e = &h->ev[h->ev_used];
-                h->ev_used += 5;
-                HIP_CHECK(hipEventRecord(e[0], h->stream));
+        const StateSet& cur = cur_set(h);
+        KP k = read_kp(h);
+        const T* src = (const T*)cur.pop;
+        T* dst = (T*)dst_set.pop;
+        float4* Rout = dst_set.R;
+        uint4* Qout = dst_set.Q;
+        float* hprev = cur.hist;
+        float* hcur = dst_set.hist;
+        hipEvent_t* e = nullptr;
+        if (h->profiling) {
+            while (h->ev.size() < h->ev_used + 5) {
+                hipEvent_t x;
+                HIP_CHECK(hipEventCreate(&x));
+                h->ev.push_back(x);
             }
-            // density pass (jet: the outlet plane by the convective condition)
-            if (jet) {
-                const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1));
-                const dim3 go((unsigned)((h->k.plane + OBLOCK - 1) / OBLOCK));
-                hipLaunchKernelGGL((k_density<BC, S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k);
-                LAUNCH_CHECK();
-                hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(OBLOCK), 0, h->stream, src, h->PD, h->XR, hprev,
-                                   hcur, k);
-            } else {
-                hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR,
-                                   k);
-            }
-            LAUNCH_CHECK();
-            if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
-            if (!kDensityGhosts<S>) {  // FP32: the density kernels fill the field ghost shell
-                hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
-                LAUNCH_CHECK();
-            }
-            if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
-            // fused collide-perturb-recolour-stream
-            hipLaunchKernelGGL((k_collide<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,
-                               hcur, Rout, Qout, k);
-            LAUNCH_CHECK();
-            if (e) HIP_CHECK(hipEventRecord(e[3], h->stream));
-            hipLaunchKernelGGL((k_pop_ghosts<BC, S>), dim3((h->ncells + GBLOCK - 1) / GBLOCK), dim3(GBLOCK), 0,
-                               h->stream, dst, Rout, Qout, k, h->ncells);
-            LAUNCH_CHECK();
-            if (e) HIP_CHECK(hipEventRecord(e[4], h->stream));
-            h->cur ^= 1;
-            if (jet) h->hprev ^= 1;
-            h->t += 1;
-            h->unshifted = 0;
+            e = &h->ev[h->ev_used];
+            h->ev_used += 5;
+            HIP_CHECK(hipEventRecord(e[0], h->stream));
         }
+        // density pass (jet: the outlet plane by the convective condition)
+        if (jet) {
+            const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1));
+            const dim3 go((unsigned)((h->k.plane + OBLOCK - 1) / OBLOCK));
+            hipLaunchKernelGGL((k_density<BC, S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k,
+                               (float*)nullptr);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(OBLOCK), 0, h->stream, src, h->PD, h->XR, hprev,
+                               hcur, k, (float*)nullptr);
+        } else {
+            hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR,
+                               k, (float*)nullptr);
+        }
+        LAUNCH_CHECK();
+        if (e) HIP_CHECK(hipEventRecord(e[1], h->stream));
+        if (!kDensityGhosts<S>) {  // FP32: the density kernels fill the field ghost shell
+            hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
+            LAUNCH_CHECK();
+        }
+        if (e) HIP_CHECK(hipEventRecord(e[2], h->stream));
+        // fused collide-perturb-recolour-stream
+        hipLaunchKernelGGL((k_collide<BC, S>), h->grid_tiles, dim3(BLOCK), 0, h->stream, src, dst, h->PD, h->XR,
+                           hcur, Rout, Qout, k);
+        LAUNCH_CHECK();
+        if (e) HIP_CHECK(hipEventRecord(e[3], h->stream));
+        hipLaunchKernelGGL((k_pop_ghosts<BC, S>), dim3((h->ncells + GBLOCK - 1) / GBLOCK), dim3(GBLOCK), 0,
+                           h->stream, dst, Rout, Qout, k, h->ncells);
+        LAUNCH_CHECK();
+        if (e) HIP_CHECK(hipEventRecord(e[4], h->stream));
+        if (dst_cs == 2) h->ext = dst_set;
+        h->cs = dst_cs;
+        h->t += 1;
+        h->unshifted = 0;
         return LBM_OK;
     });
+}
+
+// the snapshot at snap, checked for alignment
+int snap_set(const lbm_handle* h, const void* snap, StateSet* s)
+{
+    if (!snap) return fail(LBM_ERR_INVALID_ARG, "snapshot pointer is NULL");
+    if (!aligned(snap, 256)) return fail(LBM_ERR_INVALID_ARG, "snapshot must be 256-byte aligned");
+    snap_layout(&h->p, (char*)snap, s);
+    return LBM_OK;
+}
+
+// copy the shifted state src into dst (device to device, on the stream)
+int copy_state(const lbm_handle* h, const StateSet& dst, const StateSet& src)
+{
+    const SnapBytes b = snap_bytes_of(&h->p);
+    if (dst.pop != src.pop) HIP_CHECK(hipMemcpyAsync(dst.pop, src.pop, b.pop, hipMemcpyDeviceToDevice, h->stream));
+    if (dst.R != src.R) HIP_CHECK(hipMemcpyAsync(dst.R, src.R, b.rec, hipMemcpyDeviceToDevice, h->stream));
+    if (src.Q && dst.Q != src.Q)
+        HIP_CHECK(hipMemcpyAsync(dst.Q, src.Q, b.rec, hipMemcpyDeviceToDevice, h->stream));
+    if (b.hist && dst.hist != src.hist)
+        HIP_CHECK(hipMemcpyAsync(dst.hist, src.hist, b.hist, hipMemcpyDeviceToDevice, h->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_step(lbm_handle* h, int32_t n_steps)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (n_steps < 0) return fail(LBM_ERR_INVALID_ARG, "n_steps < 0");
+    for (int s = 0; s < n_steps; ++s) {
+        const int d = free_own(h);
+        const int rc = step_once(h, h->own[d], d);
+        if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_step_into(lbm_handle* h, void* snap)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    StateSet s;
+    int rc = snap_set(h, snap, &s);
+    if (rc != LBM_OK) return rc;
+    const StateSet& c = cur_set(h);
+    if (s.pop == c.pop) return fail(LBM_ERR_INVALID_ARG, "the snapshot holds the current state");
+    return step_once(h, s, 2);
+}
+
+int lbm_snapshot_save(lbm_handle* h, void* snap)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (h->unshifted) return fail(LBM_ERR_STATE, "the current state is a general state (after init or set_state)");
+    StateSet s;
+    int rc = snap_set(h, snap, &s);
+    if (rc != LBM_OK) return rc;
+    return copy_state(h, s, cur_set(h));
+}
+
+int lbm_snapshot_load(lbm_handle* h, const void* snap, int64_t t)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
+    StateSet s;
+    int rc = snap_set(h, snap, &s);
+    if (rc != LBM_OK) return rc;
+    const int d = h->cs == 2 ? 0 : h->cs;
+    rc = copy_state(h, h->own[d], s);
+    if (rc != LBM_OK) return rc;
+    h->cs = d;
+    h->t = t;
+    h->unshifted = 0;
+    return LBM_OK;
 }
 
 int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* phi, double* audit)
@@ -364,7 +514,7 @@ int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* 
         using S = decltype(st);
         constexpr int BC = decltype(bc)::value;
         hipLaunchKernelGGL((k_macro<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
-                           (const typename S::T*)h->pop[h->cur], h->hist[h->hprev], k, rho_r, rho_b, u, phi,
+                           (const typename S::T*)cur_set(h).pop, cur_set(h).hist, k, rho_r, rho_b, u, phi,
                            audit ? h->audit : nullptr);
         LAUNCH_CHECK();
         return LBM_OK;
@@ -389,7 +539,7 @@ int lbm_get_state(lbm_handle* h, float* state)
         using S = decltype(st);
         constexpr int BC = decltype(bc)::value;
         hipLaunchKernelGGL((k_get_state<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
-                           (const typename S::T*)h->pop[h->cur], h->hist[h->hprev], k, state, (double)h->k.rho_b0);
+                           (const typename S::T*)cur_set(h).pop, cur_set(h).hist, k, state, (double)h->k.rho_b0);
         LAUNCH_CHECK();
         return LBM_OK;
     });
@@ -400,16 +550,19 @@ int lbm_set_state(lbm_handle* h, const float* state, int64_t t)
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
     if (!state) return fail(LBM_ERR_INVALID_ARG, "state is NULL");
     if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
+    // the general state goes into an own set (a current snapshot is not overwritten)
+    const int d = h->cs == 2 ? 0 : h->cs;
     const KP k = read_kp(h);
     int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         (void)bc;
-        hipLaunchKernelGGL(k_set_state<S>, h->grid_all, dim3(BLOCK), 0, h->stream, (typename S::T*)h->pop[h->cur],
-                           h->R[h->cur], k, state, (double)h->k.rho_b0);
+        hipLaunchKernelGGL(k_set_state<S>, h->grid_all, dim3(BLOCK), 0, h->stream, (typename S::T*)h->own[d].pop,
+                           h->own[d].R, k, state, (double)h->k.rho_b0);
         LAUNCH_CHECK();
         return LBM_OK;
     });
     if (rc != LBM_OK) return rc;
+    h->cs = d;
     h->t = t;
     h->unshifted = 1;
     return LBM_OK;
@@ -417,16 +570,67 @@ int lbm_set_state(lbm_handle* h, const float* state, int64_t t)
 
 int64_t lbm_time(const lbm_handle* h) { return h ? (int64_t)h->t : -1; }
 
-int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float* lambda_in, float* lambda_out,
-                     double* dJ_dA, float* dJ_du_in)
+}  // extern "C"
+
+namespace {
+
+// Passes 2-6 of the adjoint step (see lbm_adjoint.h) after pass 1 has written
+// PD, XR and the raw moments of x_t; htop/hs/dfr give the outlet plane of x_t.
+template <int BC>
+int adjoint_rest(lbm_handle* h, const KP& k, const AdjWork& w, const float* htop, size_t hs, int dfr,
+                 const float* lambda_in, float* lambda_out, double* dJ_dA, float* dJ_du_in)
+{
+    hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
+    LAUNCH_CHECK();
+    if (BC == LBM_BC_JET) {
+        KP kt = k;
+        kt.z0 = h->p.nz - 3;
+        hipLaunchKernelGGL(k_adj_top_post, dim3(h->grid_all.x, 3), dim3(BLOCK), 0, h->stream, w.MOM, h->PD, h->XR,
+                           w.PS, kt);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_adj_outlet, h->grid_plane, dim3(BLOCK), 0, h->stream, htop, hs, dfr, lambda_in, w.PS,
+                           w.ML, w.DL, k);
+        LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_adj_node<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, w.MOM, lambda_in, w.ML, h->PD, h->XR,
+                       w.LC, w.AG0, w.AG1, w.AP, k);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_adj_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, k, h->ncells);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_adj_fields<BC>, h->grid_tiles, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, h->PD, h->XR,
+                       w.DL, w.LC, lambda_out, k);
+    LAUNCH_CHECK();
+    if (BC == LBM_BC_JET && dJ_du_in) {
+        hipLaunchKernelGGL(k_adj_inlet, h->grid_plane, dim3(BLOCK), 0, h->stream, lambda_in, dJ_du_in, k);
+        LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_adj_sumA, dim3(1), dim3(SUM_BLOCK), 0, h->stream, w.AP, h->nblk, dJ_dA);
+    LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+int adjoint_args(lbm_handle* h, const void* state_t, int64_t t, const float* lambda_in, float* lambda_out,
+                 double* dJ_dA)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
     if (!h->adjoint) return fail(LBM_ERR_STATE, "no adjoint work buffer was given to lbm_init");
     if (!state_t || !lambda_in || !lambda_out || !dJ_dA)
         return fail(LBM_ERR_INVALID_ARG, "state_t, lambda_in, lambda_out and dJ_dA are required");
-    if (lambda_out == lambda_in || (const float*)lambda_out == state_t)
+    if (lambda_out == lambda_in || (const void*)lambda_out == state_t)
         return fail(LBM_ERR_INVALID_ARG, "lambda_out must not alias lambda_in or state_t");
     if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float* lambda_in, float* lambda_out,
+                     double* dJ_dA, float* dJ_du_in)
+{
+    int rc = adjoint_args(h, state_t, t, lambda_in, lambda_out, dJ_dA);
+    if (rc != LBM_OK) return rc;
     AdjWork w;
     adjoint_layout(h->k.NP, h->k.N, h->k.plane, (uint64_t)h->nblk, (char*)h->adjoint, &w);
     KP k = h->k;
@@ -434,41 +638,55 @@ int lbm_adjoint_step(lbm_handle* h, const float* state_t, int64_t t, const float
     k.unshifted = 1;
     k.z0 = 0;
     k.R = nullptr;
-    auto run = [&](auto bc) -> int {
+    hipLaunchKernelGGL(k_adj_density, h->grid_all, dim3(BLOCK), 0, h->stream, state_t, h->PD, h->XR, w.MOM, k);
+    LAUNCH_CHECK();
+    const float* top = state_t + (size_t)(h->p.nz - 1) * h->k.plane;
+    if (h->p.bc == LBM_BC_PERIODIC)
+        return adjoint_rest<LBM_BC_PERIODIC>(h, k, w, top, h->k.N, 0, lambda_in, lambda_out, dJ_dA, dJ_du_in);
+    return adjoint_rest<LBM_BC_JET>(h, k, w, top, h->k.N, 0, lambda_in, lambda_out, dJ_dA, dJ_du_in);
+}
+
+int lbm_adjoint_step_snapshot(lbm_handle* h, const void* snap_t, int64_t t, const float* lambda_in,
+                              float* lambda_out, double* dJ_dA, float* dJ_du_in)
+{
+    int rc = adjoint_args(h, snap_t, t, lambda_in, lambda_out, dJ_dA);
+    if (rc != LBM_OK) return rc;
+    StateSet s;
+    rc = snap_set(h, snap_t, &s);
+    if (rc != LBM_OK) return rc;
+    AdjWork w;
+    adjoint_layout(h->k.NP, h->k.N, h->k.plane, (uint64_t)h->nblk, (char*)h->adjoint, &w);
+    KP k = h->k;
+    k.t = t;
+    k.unshifted = 0;
+    k.z0 = 0;
+    k.R = s.R;
+    k.Qrec = s.Q;
+    k.xr_tagged = 1;
+    // pass 1 from the snapshot: the forward density pass (pulled deviations,
+    // (phi, rho), tagged colour fraction) plus the raw moments
+    rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
+        using S = decltype(st);
         constexpr int BC = decltype(bc)::value;
-        hipLaunchKernelGGL(k_adj_density, h->grid_all, dim3(BLOCK), 0, h->stream, state_t, h->PD, h->XR, w.MOM, k);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_field_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, h->PD, k, h->ncells);
-        LAUNCH_CHECK();
+        const typename S::T* src = (const typename S::T*)s.pop;
         if (BC == LBM_BC_JET) {
-            KP kt = k;
-            kt.z0 = h->p.nz - 3;
-            hipLaunchKernelGGL(k_adj_top_post, dim3(h->grid_all.x, 3), dim3(BLOCK), 0, h->stream, w.MOM, h->PD,
-                               h->XR, w.PS, kt);
+            const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1));
+            const dim3 go((unsigned)((h->k.plane + OBLOCK - 1) / OBLOCK));
+            hipLaunchKernelGGL((k_density<BC, S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k, w.MOM);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_adj_outlet, h->grid_plane, dim3(BLOCK), 0, h->stream, state_t, lambda_in, w.PS,
-                               w.ML, w.DL, k);
-            LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(OBLOCK), 0, h->stream, src, h->PD, h->XR, s.hist,
+                               w.ST, k, w.MOM);
+        } else {
+            hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k,
+                               w.MOM);
         }
-        hipLaunchKernelGGL(k_adj_node<BC>, h->grid_all, dim3(BLOCK), 0, h->stream, w.MOM, lambda_in, w.ML, h->PD,
-                           h->XR, w.LC, w.AG0, w.AG1, w.AP, k);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_adj_ghosts<BC>, h->grid_shell, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, k,
-                           h->ncells);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_adj_fields<BC>, h->grid_tiles, dim3(BLOCK), 0, h->stream, w.AG0, w.AG1, w.GH, h->PD,
-                           h->XR, w.DL, w.LC, lambda_out, k);
-        LAUNCH_CHECK();
-        if (BC == LBM_BC_JET && dJ_du_in) {
-            hipLaunchKernelGGL(k_adj_inlet, h->grid_plane, dim3(BLOCK), 0, h->stream, lambda_in, dJ_du_in, k);
-            LAUNCH_CHECK();
-        }
-        hipLaunchKernelGGL(k_adj_sumA, dim3(1), dim3(SUM_BLOCK), 0, h->stream, w.AP, h->nblk, dJ_dA);
         LAUNCH_CHECK();
         return LBM_OK;
-    };
-    if (h->p.bc == LBM_BC_PERIODIC) return run(IntC<LBM_BC_PERIODIC>{});
-    return run(IntC<LBM_BC_JET>{});
+    });
+    if (rc != LBM_OK) return rc;
+    if (h->p.bc == LBM_BC_PERIODIC)
+        return adjoint_rest<LBM_BC_PERIODIC>(h, k, w, w.ST, h->k.plane, 1, lambda_in, lambda_out, dJ_dA, dJ_du_in);
+    return adjoint_rest<LBM_BC_JET>(h, k, w, w.ST, h->k.plane, 1, lambda_in, lambda_out, dJ_dA, dJ_du_in);
 }
 
 int lbm_profile(lbm_handle* h, int enable)
@@ -533,7 +751,7 @@ int lbm_jet_diagnostics(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t
         hipLaunchKernelGGL(k_diag_clear, dim3(1), dim3(64), 0, h->stream, w);
         LAUNCH_CHECK();
         hipLaunchKernelGGL((k_diag_init<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
-                           (const typename S::T*)h->pop[h->cur], h->hist[h->hprev], k, w);
+                           (const typename S::T*)cur_set(h).pop, cur_set(h).hist, k, w);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_diag_merge, h->grid_all, dim3(BLOCK), 0, h->stream, k, w);
         LAUNCH_CHECK();

@@ -37,6 +37,7 @@ struct AdjWork {
     float* PS;      // jet: post-collision populations of the top three planes [54][3][plane]
     float* ML;      // jet: cotangent of the streamed plane nz - 2 incl. the outlet condition [54][plane]
     float* DL;      // jet: direct outlet term of lambda_t at plane nz - 1 [54][plane]
+    float* ST;      // jet, state from a snapshot: the outlet plane of x_t as (d, f^r) [54][plane]
     double* AP;     // dJ/dA block partials
 };
 
@@ -58,6 +59,7 @@ inline uint64_t adjoint_layout(uint64_t NP, uint64_t N, uint64_t plane, uint64_t
     char* ps = take(2ull * Q * 3 * plane * 4);
     char* ml = take(2ull * Q * plane * 4);
     char* dl = take(2ull * Q * plane * 4);
+    char* sp = take(2ull * Q * plane * 4);
     char* ap = take((nblk + 1) * 8);
     if (w) {
         w->MOM = (float*)mom;
@@ -68,6 +70,7 @@ inline uint64_t adjoint_layout(uint64_t NP, uint64_t N, uint64_t plane, uint64_t
         w->PS = (float*)ps;
         w->ML = (float*)ml;
         w->DL = (float*)dl;
+        w->ST = (float*)sp;
         w->AP = (double*)ap;
     }
     return off;
@@ -118,6 +121,7 @@ __device__ __forceinline__ void adj_node_fwd(const KP& k, const float* __restric
     for (int a = 0; a < 6; ++a) M.P[a] = MOM[(size_t)(4 + a) * N + n];
     const float phic = ldp(PD, nd.n).x;
     xr = ldp(XR, nd.n);
+    if (k.xr_tagged) xr = frac_of(xr, 0u);
     double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     gradients(PD, k, nd.n, g);
     node_fwd<float>(k, M, phic, g, f);
@@ -148,7 +152,19 @@ __global__ __launch_bounds__(BLOCK) void k_adj_top_post(const float* __restrict_
 // y = the streamed populations of plane nz - 2, h = the state's plane nz - 1.
 // Writes ML = cotangent of y (lambda of plane nz - 2 plus the outlet terms) and
 // DL = lambda of plane nz - 1 / (1 + lam) (the direct dependence on h).
-__global__ __launch_bounds__(BLOCK) void k_adj_outlet(const float* __restrict__ st, const float* __restrict__ lam_in,
+// h comes as (f^r, f^b) planes of stride hs (dfr = 0) or as the (d, f^r)
+// planes of stride plane that the density pass of a snapshot wrote (dfr = 1).
+__device__ __forceinline__ double top_value(const KP& k, const float* __restrict__ h, size_t hs, int dfr, int j,
+                                            uint32_t q)
+{
+    if (!dfr) return h[(size_t)j * hs + q];
+    if (j < Q) return h[(size_t)(Q + j) * k.plane + q];
+    const int i = j - Q;
+    return ((double)h[(size_t)i * k.plane + q] + wgtd(i) * (double)k.rho_b0) - (double)h[(size_t)(Q + i) * k.plane + q];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adj_outlet(const float* __restrict__ htop, size_t hs, int dfr,
+                                                       const float* __restrict__ lam_in,
                                                        const float* __restrict__ PS, float* __restrict__ ML,
                                                        float* __restrict__ DL, KP k)
 {
@@ -181,7 +197,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_outlet(const float* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 2 * Q; ++j) {
         const double L1 = lam_in[(size_t)j * N + ntop];
-        const double h = st[(size_t)j * N + ntop];
+        const double h = top_value(k, htop, hs, dfr, j, q);
         Llam += L1 * ((double)yv[j] - h) * inv * inv;
     }
     const double Luz = uz > 0.0 ? Llam : 0.0;
@@ -372,7 +388,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fields(const float4* __restrict__
     // phi = (a - b)/(a + b), a = rho_r/rho_r0, b = rho_b/rho_b0; rho_r/rho; rho
     const float2 pd = ldp(PD, nd.n);
     const double rho = (double)k.rho_b0 + (double)pd.y;
-    const double rr = (double)ldp(XR, nd.n) * rho, rb = rho - rr;
+    const float xrn = k.xr_tagged ? frac_of(ldp(XR, nd.n), 0u) : ldp(XR, nd.n);
+    const double rr = (double)xrn * rho, rb = rho - rr;
     const double a = rr / (double)k.rho_r0, b = rb / (double)k.rho_b0;
     const double ab2 = (a + b) * (a + b);
     const float Lrr = (float)(Lphi * 2.0 * b / (ab2 * (double)k.rho_r0) + Lrf + Lxr * rb / (rho * rho));

@@ -118,6 +118,7 @@ struct KP {
     uint64_t seed;
     long long t;       // time level of the state that is read
     int unshifted;     // general state (54 planes) stored without the streaming shift
+    int xr_tagged;     // adjoint passes: XR holds the tagged minority fraction (else rho_r / rho)
     const float* inlet_uz;
     const float4* R;   // (tagged minority fraction, V) of the state that is read
     const uint4* Qrec; // referenced 16-bit storage: reference record of the state that is read
@@ -747,6 +748,29 @@ __device__ __forceinline__ void accum_density_win(const KP& k, const float* d, c
     }
 }
 
+// Raw moments of the deviations up to second order -- m0, j (3), P (xx, yy,
+// zz, xy, xz, yz) -- as 10 planes of N floats at node index nn (z plane + q),
+// for the adjoint step; j and P are FP32 sums over opposite pairs.
+__device__ __forceinline__ void store_moments(float* __restrict__ MOM, const KP& k, uint32_t nn, float m0,
+                                              const float* d)
+{
+    float jx = 0.f, jy = 0.f, jz = 0.f, pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const float sp = d[i] + d[i + 1], df = d[i] - d[i + 1];
+        if (kCX[i]) { jx += kCX[i] * df; pxx += sp; }
+        if (kCY[i]) { jy += kCY[i] * df; pyy += sp; }
+        if (kCZ[i]) { jz += kCZ[i] * df; pzz += sp; }
+        if (kCX[i] * kCY[i]) pxy += (kCX[i] * kCY[i]) * sp;
+        if (kCX[i] * kCZ[i]) pxz += (kCX[i] * kCZ[i]) * sp;
+        if (kCY[i] * kCZ[i]) pyz += (kCY[i] * kCZ[i]) * sp;
+    }
+    const float mv[10] = {m0, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz};
+    const size_t N = k.N;
+#pragma unroll
+    for (int a = 0; a < 10; ++a) MOM[(size_t)a * N + nn] = mv[a];
+}
+
 // Density pass over the planes of the grid (for the jet all but the outlet
 // plane, which k_outlet_density takes: its branch would double this kernel's
 // register count and halve its occupancy).  With FP32 storage it also fills
@@ -766,8 +790,11 @@ constexpr int kDensityWaves = (sizeof(typename S::T) == 2 && !S::kEqRef) ? 8 : 2
 
 template <int BC, class S>
 __global__ __launch_bounds__(DBLOCK) __attribute__((amdgpu_waves_per_eu(kDensityWaves<S>, 8))) void k_density(
-    const typename S::T* __restrict__ src, float2* __restrict__ PD, float* __restrict__ XR, KP k)
+    const typename S::T* __restrict__ src, float2* __restrict__ PD, float* __restrict__ XR, KP k,
+    float* __restrict__ MOM)
 {
+    // MOM != NULL (adjoint step from a snapshot): also the raw moments of the
+    // pulled deviations
     __shared__ float4 win[TileShape<DTY>::W];
     const Tile t = this_tile<DTY>(k);
     const Node& nd = t.nd;
@@ -799,6 +826,7 @@ __global__ __launch_bounds__(DBLOCK) __attribute__((amdgpu_waves_per_eu(kDensity
     mk = (double)x0 * rho + (double)(cf + (bl ? -cv : cv));
     const float2 v = store_fields_sums(PD, XR, k, nd.n, m0, bl ? rho - mk : mk, bl ? mk : rho - mk);
     if constexpr (kDensityGhosts<S>) store_pd_ghosts<BC>(PD, k, nd.x, nd.y, nd.z, v);
+    if (MOM) store_moments(MOM, k, (uint32_t)nd.z * k.plane + nd.q, (float)m0, d);
 }
 
 // Jet outlet plane (z = nz - 1): its state by the convective condition,
@@ -810,7 +838,7 @@ template <class S>
 __global__ __launch_bounds__(OBLOCK) void k_outlet_density(const typename S::T* __restrict__ src,
                                                             float2* __restrict__ PD, float* __restrict__ XR,
                                                             const float* __restrict__ hprev, float* __restrict__ hcur,
-                                                            KP k)
+                                                            KP k, float* __restrict__ MOM)
 {
     const uint32_t q = blockIdx.x * OBLOCK + threadIdx.x;
     if (q >= k.plane) return;
@@ -830,6 +858,7 @@ __global__ __launch_bounds__(OBLOCK) void k_outlet_density(const typename S::T* 
     }
     const float2 v = store_fields(PD, XR, k, nd.n, d, fr);
     if constexpr (kDensityGhosts<S>) store_pd_ghosts<LBM_BC_JET>(PD, k, nd.x, nd.y, nd.z, v);
+    if (MOM) store_moments(MOM, k, (uint32_t)nd.z * k.plane + nd.q, v.y, d);
 }
 
 

@@ -46,7 +46,7 @@ class lbm_params(C.Structure):
 
 class lbm_sizes(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("n_nodes", "pop_bytes", "field_bytes", "hist_bytes", "audit_bytes",
-                                          "inlet_bytes", "adjoint_bytes", "state_bytes")]
+                                          "inlet_bytes", "adjoint_bytes", "state_bytes", "snap_bytes")]
 
 
 class lbm_jet_stats(C.Structure):
@@ -59,7 +59,8 @@ class lbm_buffers(C.Structure):
 
 
 EXPORTS = ("lbm_query_sizes", "lbm_init", "lbm_step", "lbm_macroscopic", "lbm_get_state", "lbm_set_state",
-           "lbm_time", "lbm_adjoint_step", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
+           "lbm_time", "lbm_step_into", "lbm_snapshot_save", "lbm_snapshot_load", "lbm_adjoint_step",
+           "lbm_adjoint_step_snapshot", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
            "lbm_profile_read", "lbm_destroy", "lbm_status_string", "lbm_last_error")
 
 _lib = None
@@ -83,6 +84,10 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_time.argtypes = [vp]
     lib.lbm_time.restype = i64
     lib.lbm_adjoint_step.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
+    lib.lbm_adjoint_step_snapshot.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
+    lib.lbm_step_into.argtypes = [vp, vp]
+    lib.lbm_snapshot_save.argtypes = [vp, vp]
+    lib.lbm_snapshot_load.argtypes = [vp, vp, i64]
     lib.lbm_diag_bytes.argtypes = [C.POINTER(lbm_params), C.POINTER(C.c_uint64)]
     lib.lbm_jet_diagnostics.argtypes = [vp, vp, C.POINTER(lbm_jet_stats), C.POINTER(C.c_int64), C.c_int64]
     lib.lbm_profile.argtypes = [vp, C.c_int]
@@ -92,7 +97,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_status_string.restype = C.c_char_p
     lib.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_query_sizes", "lbm_init", "lbm_step", "lbm_macroscopic", "lbm_get_state",
-                 "lbm_set_state", "lbm_adjoint_step", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
+                 "lbm_set_state", "lbm_step_into", "lbm_snapshot_save", "lbm_snapshot_load", "lbm_adjoint_step",
+                 "lbm_adjoint_step_snapshot", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
                  "lbm_profile_read", "lbm_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -211,6 +217,27 @@ class LBM:
     def time(self) -> int:
         return int(self.lib.lbm_time(self.h))
 
+    # -- snapshots (lbm_step_into, lbm_snapshot_save / _load) ----------------
+    def new_snapshot(self):
+        """An uninitialised device buffer of snap_bytes (256-byte aligned)."""
+        return self.torch.empty(int(self.sizes.snap_bytes), dtype=self.torch.uint8, device=self.device)
+
+    def _snap(self, snap):
+        assert snap.dtype == self.torch.uint8 and snap.numel() >= self.sizes.snap_bytes and snap.is_contiguous()
+        return snap.data_ptr()
+
+    def step_to_snapshot(self, snap):
+        """One step written into ``snap``, which becomes the current state (it
+        must not be modified until the next step or load)."""
+        _check(self.lib, self.lib.lbm_step_into(self.h, self._snap(snap)))
+        self._current_snapshot = snap
+
+    def save_snapshot(self, snap):
+        _check(self.lib, self.lib.lbm_snapshot_save(self.h, self._snap(snap)))
+
+    def load_snapshot(self, snap, t: int):
+        _check(self.lib, self.lib.lbm_snapshot_load(self.h, self._snap(snap), int(t)))
+
     def adjoint_step(self, state_t, t: int, lam_in, lam_out, dJ_dA, dJ_du_in=None):
         """One reverse step (see lbm_adjoint_step): lam_out = (d x_{t+1}/d x_t)^T lam_in;
         dJ_dA (float64, 1 element) and dJ_du_in (float32, nx*ny) are incremented."""
@@ -221,6 +248,16 @@ class LBM:
             assert dJ_du_in.dtype == self.torch.float32 and dJ_du_in.numel() == self.prob.nx * self.prob.ny
         _check(self.lib, self.lib.lbm_adjoint_step(self.h, state_t.data_ptr(), int(t), lam_in.data_ptr(),
                                                    lam_out.data_ptr(), dJ_dA.data_ptr(), _ptr(dJ_du_in)))
+
+    def adjoint_step_snapshot(self, snap_t, t: int, lam_in, lam_out, dJ_dA, dJ_du_in=None):
+        """adjoint_step with the forward state at time t given as a snapshot."""
+        for a in (lam_in, lam_out):
+            assert a.dtype == self.torch.float32 and a.is_contiguous() and a.numel() == 2 * Q * self.sizes.n_nodes
+        assert dJ_dA.dtype == self.torch.float64 and dJ_dA.numel() >= 1
+        if dJ_du_in is not None:
+            assert dJ_du_in.dtype == self.torch.float32 and dJ_du_in.numel() == self.prob.nx * self.prob.ny
+        _check(self.lib, self.lib.lbm_adjoint_step_snapshot(self.h, self._snap(snap_t), int(t), lam_in.data_ptr(),
+                                                            lam_out.data_ptr(), dJ_dA.data_ptr(), _ptr(dJ_du_in)))
 
     def jet_diagnostics(self, cap: Optional[int] = None):
         """Leading edge and fragments of the jet phase (lbm_jet_diagnostics):

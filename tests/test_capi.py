@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(lbm.EXPORTS)
-    assert len(names) == 15
+    assert len(names) == 19
 
 
 def test_query_sizes(lib):
@@ -45,6 +45,10 @@ def test_query_sizes(lib):
         assert s.state_bytes == 54 * N * 4
         assert s.field_bytes == 44 * NP
         assert s.hist_bytes == (2 * 54 * prob.nx * prob.ny * 4 if prob.bc == "jet" else 0)
+        # snapshot: 27 FP32 planes, one 16-byte record per padded node, the jet's outlet plane
+        a = lambda b: (b + 255) // 256 * 256
+        assert s.snap_bytes == a(27 * NP * 4) + a(16 * NP) + (a(2 * 27 * prob.nx * prob.ny * 4) if prob.bc == "jet"
+                                                              else 0)
         for st, b, fb in (("bf16", 2, 44), ("fp16", 2, 44), ("bf16eq", 2, 76), ("fp16eq", 2, 76)):
             s2 = lbm.lbm_query_sizes(lbm.make_params(prob.replace(storage=st)))
             assert s2.pop_bytes == 54 * NP * b
@@ -74,6 +78,22 @@ def test_jet_minimum_size(lib):
     p = lbm.make_params(jet_128().replace(nz=2))
     s = lbm.lbm_sizes()
     assert lib.lbm_query_sizes(C.byref(p), C.byref(s)) == -1
+
+
+def test_inlet_touching_a_side_wall_is_rejected(lib):
+    s = lbm.lbm_sizes()
+    ok = jet_128()
+    assert lib.lbm_query_sizes(C.byref(lbm.make_params(ok)), C.byref(s)) == 0
+    for bad in (ok.replace(inlet_D=130.0), ok.replace(inlet_cx=1.0), ok.replace(inlet_cy=126.5, inlet_D=4.0)):
+        assert lib.lbm_query_sizes(C.byref(lbm.make_params(bad)), C.byref(s)) == -1
+        assert "inlet" in lib.lbm_last_error().decode()
+
+
+def test_snapshot_entry_points_reject_null_handles(lib):
+    assert lib.lbm_step_into(None, None) == -5
+    assert lib.lbm_snapshot_save(None, None) == -5
+    assert lib.lbm_snapshot_load(None, None, 0) == -5
+    assert lib.lbm_adjoint_step_snapshot(None, None, 0, None, None, None, None) == -5
 
 
 def test_status_strings(lib):

@@ -8,11 +8,16 @@ parameter gradients <w, dS/dA> and <w, dS/du_in>.  Checked:
     near a wall, the inlet or the outlet there);
   * dot products with random and boundary-supported directions, dJ/dA and
     dJ/du_in on lattices of several 256-node blocks;
+  * the same reverse step with the forward state given as a snapshot (the
+    library's own layout, lbm_adjoint_step_snapshot), element by element;
+  * snapshots: stepping into snapshots, saving and loading them reproduce
+    plain stepping bit for bit;
   * a checkpointed multi-step gradient through the torch.autograd binding
-    against complex step and central differences of the FP64 oracle.
-Tolerances: the adjoint runs in FP64 per node with FP32 storage of the
-cotangents, so single-step results agree to ~1e-6 relative; the target
-bar for gradients is 1e-4 relative.
+    (checkpoints and recomputed states as snapshots) against complex step and
+    central differences of the FP64 oracle.
+Tolerances: the adjoint's node arithmetic is FP32 (FP64 only for the dJ/dA
+and dJ/du_in accumulations), so single-step results agree to ~1e-6 relative;
+the target bar for gradients is 1e-4 relative.
 """
 import numpy as np
 import pytest
@@ -175,6 +180,104 @@ def test_adjoint_dot_products(torch, orc, orc_cs, case):
     if prob.bc == "jet":
         e = rng.standard_normal(nx * ny)
         _dot_check("dJ/du_in . e", float((du * e).sum()), w64, _cs_step(orc_cs, prob, st64, t, inlet=inlet, du=e))
+
+
+def _gpu_snapshot_case(torch, prob, st32, t_start, nsteps, w32, inlet=None):
+    """From st32 at time t_start, step nsteps - 1 times and once more into a
+    snapshot; return the FP32 state there (lbm_get_state) and the reverse
+    step from the snapshot."""
+    from paper_1804_08923_amd.lbm import LBM
+    sim = LBM(prob, adjoint=True, inlet_uz=inlet)
+    dev = sim.device
+    sim.set_state(torch.from_numpy(st32).to(dev), t_start)
+    sim.step(nsteps - 1)
+    snap = sim.new_snapshot()
+    sim.step_to_snapshot(snap)
+    t = sim.time
+    x_t = sim.get_state().cpu().numpy()
+    lam_in = torch.from_numpy(w32).to(dev)
+    lam_out = torch.empty_like(lam_in)
+    dA = torch.zeros(1, dtype=torch.float64, device=dev)
+    du = torch.zeros(prob.nx * prob.ny, dtype=torch.float32, device=dev)
+    sim.adjoint_step_snapshot(snap, t, lam_in, lam_out, dA, du)
+    torch.cuda.synchronize()
+    out = lam_out.cpu().numpy().astype(np.float64), float(dA.item()), du.cpu().numpy().astype(np.float64)
+    sim.close()
+    return t, x_t, out
+
+
+@pytest.mark.parametrize("case", ["periodic-4x3x3", "jet-5x5x4", "jet-6x5x3"])
+def test_adjoint_from_snapshot_every_element(torch, orc, orc_cs, case):
+    """The reverse step with x_t given as a snapshot: J^T w element by element
+    against complex step of the oracle at the same state (its FP32 copy from
+    lbm_get_state), and dJ/dA, dJ/du_in by dot products."""
+    prob = {"periodic-4x3x3": _periodic(4, 3, 3), "jet-5x5x4": _jet(5, 5, 4, D=3.2),
+            "jet-6x5x3": _jet(6, 5, 3, D=3.0, g=(0.0, 0.0, -3e-5))}[case]
+    say(f"adjoint from a snapshot, every element {case}")
+    st32, _ = _state(orc, prob, seed=13)
+    rng = np.random.default_rng(14)
+    w32 = rng.standard_normal(st32.shape).astype(np.float32)
+    inlet = _inlet_profile(prob, 6) if prob.bc == "jet" else None
+    t, x_t, (lam, dA, du) = _gpu_snapshot_case(torch, prob, st32, 4, 3, w32, inlet)
+    assert t == 7
+    st64 = x_t.astype(np.float64)
+    N = prob.n_nodes
+    ref = np.zeros_like(lam)
+    w64 = w32.astype(np.float64)
+    for k in range(2 * Q):
+        for n in range(N):
+            v = np.zeros_like(st64)
+            v[k, n] = 1.0
+            ref[k, n] = (w64 * _cs_step(orc_cs, prob, st64, t, v=v, inlet=inlet)).sum()
+    err = np.abs(lam - ref).max() / np.abs(ref).max()
+    say(f"  max |J^T w - ref| / max |ref| = {err:.2e}")
+    # the snapshot holds the state the FP32 copy rounds: the Jacobians differ at that level
+    assert err < 1e-5
+    _dot_check("dJ/dA", dA, w64, _cs_step(orc_cs, prob, st64, t, dA=1.0, inlet=inlet), tol=1e-5)
+    if prob.bc == "jet":
+        e = rng.standard_normal(prob.nx * prob.ny)
+        _dot_check("dJ/du_in . e", float((du * e).sum()), w64, _cs_step(orc_cs, prob, st64, t, inlet=inlet, du=e),
+                   tol=1e-5)
+
+
+@pytest.mark.parametrize("case,storage", [("periodic-16x12x10", "fp32"), ("jet-14x12x10", "fp32"),
+                                          ("jet-14x12x10", "bf16"), ("jet-14x12x10", "fp16eq")])
+def test_snapshots_reproduce_plain_steps(torch, orc, case, storage):
+    """lbm_step_into, lbm_snapshot_save and lbm_snapshot_load change nothing
+    about the run: the states agree bit for bit with plain stepping."""
+    from paper_1804_08923_amd.lbm import LBM
+    prob = {"periodic-16x12x10": _periodic(16, 12, 10), "jet-14x12x10": _jet(14, 12, 10, D=6)}[case]
+    prob = prob.replace(storage=storage)
+    say(f"snapshots {case} {storage}")
+    st32, _ = _state(orc, prob, seed=5)
+    dev = torch.device("cuda:0")
+    x0 = torch.from_numpy(st32).to(dev)
+
+    def run(plan):
+        sim = LBM(prob, adjoint=True)
+        sim.set_state(x0, 2)
+        snaps = []
+        for op in plan:
+            if op == "s":
+                sim.step(1)
+            elif op == "i":
+                snaps.append(sim.new_snapshot())
+                sim.step_to_snapshot(snaps[-1])
+            elif op == "v":
+                snaps.append(sim.new_snapshot())
+                sim.save_snapshot(snaps[-1])
+                saved_t = sim.time
+            elif op == "l":
+                sim.load_snapshot(snaps[-1], saved_t)
+        out = sim.get_state().cpu().numpy(), sim.time
+        sim.close()
+        return out
+
+    ref, tr = run("sssssss")
+    for plan in ("ssiisss", "iiiiiii", "ssvsssl" + "sssss"):
+        got, tg = run(plan)
+        assert tg == tr, (plan, tg, tr)
+        assert np.array_equal(got, ref), plan
 
 
 def _objective_np(prob, fr, fb, z_lo):

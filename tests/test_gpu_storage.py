@@ -8,8 +8,10 @@ arithmetic) through the C ABI.
   conversions (the library encodes with the gfx950 conversion instructions).
 * Error against the FP64 oracle, per field (rho, u, phi), for every storage
   form on a jet with the same boundaries, buoyancy and inlet noise as the
-  128x128x512 workload, at steps 100 and 300.  Accuracy target: velocity
-  error <= 1e-3 u_max; met by FP32 and the equilibrium-referenced FP16 form.
+  benchmark jets, at steps 100 and 300.  Accuracy target: velocity error
+  <= 1e-3 u_max; met by FP32 and the equilibrium-referenced FP16 form; the
+  others are strict expected failures against it, and every form is also
+  held to its measured level (regression bounds).
 """
 import numpy as np
 import pytest
@@ -64,42 +66,82 @@ def test_codec_round_trip(torch, orc, storage):
     say(f"{storage}: codec matches torch RNE on {fk_in.size} minority-colour values and deviations")
 
 
-def test_storage_error_vs_oracle(torch, orc):
-    """Per-field error of FP32 / BF16 / FP16 storage against the FP64 oracle on
-    a 32x32x64 jet (gamma = 2, Re = 100, We = 30, Fr = 10, 1 % inlet noise)."""
-    from paper_1804_08923_amd.lbm import LBM
+JET_STEPS = (100, 300)
+# accuracy target of the reduced-precision storage: velocity error against the
+# FP64 oracle at most 1e-3 of the largest velocity
+U_BAR = 1e-3
+MISSES_BAR = {
+    "bf16": "plain BF16 rounds the velocity part of the equilibrium in every stored deviation "
+            "(about 2^-9 x 8e-3 per step): ~1.7e-2 after 100 steps",
+    "fp16": "plain FP16 rounds the same velocity part at 2^-12: ~1.2e-3 after 100 steps",
+    "bf16eq": "referenced BF16 still rounds the non-equilibrium stress, of order w_i 2.5e-3 at tau ~ 0.51: ~2e-3",
+}
+
+
+@pytest.fixture(scope="module")
+def jet_reference(orc):
+    """The 32x32x64 jet and the FP64 oracle's fields at JET_STEPS."""
     base = jet_problem("jet-32x32x64", 32, 32, 64, D=10, u=0.04, gamma=2.0, eta=1.0, Re=100.0, We=30.0,
                        Fr=10.0, steps=300, noise_amp=0.01, noise_seed=20180423)
-    checkpoints = (100, 300)
     p, fr, fb, h = oracle_init(orc, base)
     ref = {}
     done = 0
-    for s in checkpoints:
+    for s in JET_STEPS:
         orc.step(p, base.A, fr, fb, h, done, s - done)
         done = s
         ref[s] = oracle_fields(orc, p, fr, fb)
-    report = {}
-    for storage in ("fp32", "bf16", "fp16", "bf16eq", "fp16eq"):
-        sim = LBM(base.replace(storage=storage))
-        done = 0
-        for s in checkpoints:
-            sim.step(s - done)
-            done = s
-            g = gpu_fields(sim)
-            umax = np.linalg.norm(ref[s]["u"], axis=1).max()
-            e = {f: rel_linf(g[f], ref[s][f]) for f in ("rho", "u", "phi")}
-            report[(storage, s)] = e
-            say(f"  {storage} step {s}: rel Linf rho {e['rho']:.2e} u {e['u']:.2e} (u_max {umax:.3e}) "
-                f"phi {e['phi']:.2e}")
-        sim.close()
-    # Bounds: FP32 to its storage floor; the equilibrium-referenced FP16 form
-    # meets the accuracy target u error <= 1e-3 u_max.  The others do not, and
-    # are held to the levels measured on MI355X (regression bounds): plain
-    # BF16 / FP16 round the equilibrium's velocity part of every stored
-    # deviation (~1.7e-2 / ~1.1e-3 after 100 steps); referenced BF16 still
-    # rounds the non-equilibrium stress, which at tau ~ 0.51 is itself of order
-    # w_i 2.5e-3 (~2e-3).
+    return base, ref
+
+
+_errors = {}
+
+
+def _storage_errors(torch, jet_reference, storage):
+    if storage in _errors:
+        return _errors[storage]
+    from paper_1804_08923_amd.lbm import LBM
+    base, ref = jet_reference
+    sim = LBM(base.replace(storage=storage))
+    done = 0
+    out = {}
+    for s in JET_STEPS:
+        sim.step(s - done)
+        done = s
+        g = gpu_fields(sim)
+        umax = np.linalg.norm(ref[s]["u"], axis=1).max()
+        e = {f: rel_linf(g[f], ref[s][f]) for f in ("rho", "u", "phi")}
+        out[s] = e
+        say(f"  {storage} step {s}: rel Linf rho {e['rho']:.2e} u {e['u']:.2e} (u_max {umax:.3e}) "
+            f"phi {e['phi']:.2e}")
+    sim.close()
+    _errors[storage] = out
+    return out
+
+
+@pytest.mark.parametrize("storage", [
+    "fp32", "fp16eq",
+    pytest.param("bf16", marks=pytest.mark.xfail(strict=True, reason=MISSES_BAR["bf16"])),
+    pytest.param("fp16", marks=pytest.mark.xfail(strict=True, reason=MISSES_BAR["fp16"])),
+    pytest.param("bf16eq", marks=pytest.mark.xfail(strict=True, reason=MISSES_BAR["bf16eq"])),
+])
+def test_storage_velocity_error_meets_bar(torch, jet_reference, storage):
+    """Velocity error of each storage form against the FP64 oracle on a 32x32x64
+    jet (gamma = 2, Re = 100, We = 30, Fr = 10, 1 % inlet noise, the boundaries
+    and buoyancy of the benchmark jets) at steps 100 and 300, held to the
+    target u error <= 1e-3 u_max.  Forms that miss it are strict expected
+    failures: the miss stays visible, and a form that starts to pass flags
+    its stale mark."""
+    e = _storage_errors(torch, jet_reference, storage)
+    for s in JET_STEPS:
+        assert e[s]["u"] <= U_BAR, (storage, s, e[s])
+
+
+def test_storage_error_regression_bounds(torch, jet_reference):
+    """The levels measured on MI355X for every form (regression bounds, not
+    the accuracy target): a change of the codecs or the collision that makes
+    any form less accurate fails here."""
     bounds = {"fp32": 1e-4, "fp16eq": 1e-3, "bf16eq": 4e-3, "fp16": 1e-2, "bf16": 8e-2}
-    for s in checkpoints:
-        for st, b in bounds.items():
-            assert report[(st, s)]["u"] <= b, (st, s, report[(st, s)])
+    for st, b in bounds.items():
+        e = _storage_errors(torch, jet_reference, st)
+        for s in JET_STEPS:
+            assert e[s]["u"] <= b, (st, s, e[s])
