@@ -14,6 +14,13 @@ Each output ``<workload>_oracle_t<step>.npz`` holds FP32 copies of rho_r,
 rho_b, u (N x 3) and phi in node order (x fastest), plus the FP64 totals
 sum rho_r, sum rho_b and sum rho u of the FP64 state.  Progress goes to
 stdout.  Thread count: OMP_NUM_THREADS.
+
+    python tests/golden/make_jet_oracle_fields.py --sample jet-128x128x512 --steps 100,1000
+
+writes the sample the GPU comparison reads, tests/golden/cache_ship/
+<workload>_oracle_sample.npz: the fields rho, u, phi at every node with even
+x and even y (all z), per step, with the maxima of |rho|, |u|, |phi| over the
+whole lattice (the denominators of the relative errors).
 """
 from __future__ import annotations
 
@@ -40,7 +47,10 @@ def main() -> int:
     ap.add_argument("--steps", default="100,1000")
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--out", default=CACHE)
+    ap.add_argument("--sample", metavar="WORKLOAD", help="write the shipped sample of cached fields")
     a = ap.parse_args()
+    if a.sample:
+        return write_sample(a.sample, sorted(int(s) for s in a.steps.split(",")), a.out)
     prob = WORKLOADS[a.workload]()
     assert prob.bc == "jet" and prob.init == "jet"
     marks = sorted(int(s) for s in a.steps.split(","))
@@ -70,6 +80,30 @@ def main() -> int:
                  max_u=np.float64(np.linalg.norm(u, axis=1).max()), max_rho=np.float64(rho.max()))
         os.replace(path + ".tmp.npz", path)
         print(f"wrote {path}", flush=True)
+    return 0
+
+
+def write_sample(workload: str, marks, cache: str) -> int:
+    prob = WORKLOADS[workload]()
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    out = {"stride_xy": np.int64(2), "steps": np.array(marks, np.int64)}
+    for m in marks:
+        with np.load(os.path.join(cache, f"{workload}_oracle_t{m}.npz")) as f:
+            rho = (f["rho_r"].astype(np.float64) + f["rho_b"].astype(np.float64))
+            u = f["u"].reshape(nz, ny, nx, 3)
+            phi = f["phi"]
+            sel = (slice(None), slice(0, None, 2), slice(0, None, 2))
+            out[f"rho_{m}"] = rho.reshape(nz, ny, nx)[sel].astype(np.float32).ravel()
+            out[f"u_{m}"] = u[sel].reshape(-1, 3)
+            out[f"phi_{m}"] = phi.reshape(nz, ny, nx)[sel].ravel()
+            out[f"max_{m}"] = np.array([np.abs(rho).max(), np.linalg.norm(f["u"].astype(np.float64), axis=1).max(),
+                                        np.abs(phi).max()])
+            out[f"totals_{m}"] = f["totals"]
+    ship = os.path.join(HERE, "cache_ship")
+    os.makedirs(ship, exist_ok=True)
+    path = os.path.join(ship, f"{workload}_oracle_sample.npz")
+    np.savez(path, **out)
+    print(f"wrote {path}", flush=True)
     return 0
 
 

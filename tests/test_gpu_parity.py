@@ -169,13 +169,16 @@ def test_droplet_init_matches(torch, orc):
     assert np.abs(gr - fr).max() < 1e-6 and np.abs(gb - fb).max() < 1e-6
 
 
-# rel L-inf bars after 200 steps.  The 32^3 droplet carries the stated 1e-5 on
-# density and velocity.  The tau != 1, gamma = 2, gravity variant is not a stated
-# configuration: running the FP64 oracle with its state rounded to the FP32
-# (d, f^r) storage after every step already moves u by 1.3e-5, so its velocity
-# bar is set from that storage floor (x 8).
+# rel L-inf bars after 200 steps.  The 32^3 droplet (tau = 1) carries the
+# stated 1e-5 on density and velocity.  Its tau != 1, gamma = 2, gravity
+# variant (not a stated configuration) exercises the central-moment
+# relaxation at tau ~ 0.53, where the non-equilibrium stress is nearly
+# reflected every step and FP32 rounding accumulates; its velocity bar lies
+# between the two floors test_oracle_storage_floor measures on the CPU: FP32
+# storage with exact arithmetic (DROPLET_CM_U_FLOOR = 2.8e-6) and the plain
+# FP32 scheme (DROPLET_CM_U_PLAIN_FP32 = 1.9e-4).  MI355X measures 2.8e-5.
 BARS = {"droplet-32": {"rho": 1e-5, "u": 1e-5, "phi": 1e-5, "rho_r": 1e-5},
-        "droplet-32-cm": {"rho": 1e-5, "u": 1e-4, "phi": 1e-5, "rho_r": 1e-5}}
+        "droplet-32-cm": {"rho": 1e-5, "u": 5e-5, "phi": 1e-5, "rho_r": 1e-5}}
 
 
 @pytest.mark.parametrize("mk", [droplet_small, droplet_cm])
@@ -195,19 +198,59 @@ def test_droplet_200_steps(torch, orc, mk):
         say(f"  {k} rel Linf {e:.3e}  (max |{k}| = {np.abs(fo[k]).max():.3e})")
     for k, e in errs.items():
         assert e <= BARS[prob.name][k], k
+    _audit_matches_oracle(sim, fo)
+
+
+def _audit_matches_oracle(sim, fo):
+    """The five FP64 totals of lbm_macroscopic (sum rho_r, sum rho_b, sum rho u
+    with the half-force term of Eq. Momentum) against the oracle's sums of the
+    same fields: masses to 1e-6 relative (MI355X: up to 1.7e-7 after 200
+    droplet steps), momenta to 1e-5 of sum rho |u|."""
+    a = sim.macroscopic(audit=True)["audit"]
+    rho = fo["rho_r"] + fo["rho_b"]
+    ref = [fo["rho_r"].sum(), fo["rho_b"].sum(), *(rho[:, None] * fo["u"]).sum(axis=0)]
+    mscale = float((rho * np.linalg.norm(fo["u"], axis=1)).sum())
+    say(f"  audit {a} oracle {ref}")
+    for k in (0, 1):
+        assert abs(a[k] - ref[k]) <= 1e-6 * ref[k], (k, a[k], ref[k])
+    for k in (2, 3, 4):
+        assert abs(a[k] - ref[k]) <= 1e-5 * mscale, (k, a[k], ref[k], mscale)
 
 
 def test_periodic_audit_conserves(torch):
-    """FP64 audit: per-colour mass and momentum conserved on a periodic box with g = 0."""
+    """FP64 audit: per-colour mass and momentum conserved on a periodic box with
+    g = 0.  MI355X measures, over 100 steps, red 5.1e-9 and blue 1.4e-9
+    relative and momentum 2.5e-7 absolute (bit for bit the same with the
+    previous kernels); the bars leave a margin of 3 to 7.  The masses move
+    by the FP32 rounding of the stored deviations and colour fractions."""
     prob = droplet_cm().replace(g=(0.0, 0.0, 0.0))
     sim = _sim(prob)
     a0 = sim.macroscopic(audit=True)["audit"]
     sim.step(100)
     a1 = sim.macroscopic(audit=True)["audit"]
-    say(f"audit {a0} -> {a1}")
-    assert abs(a1[0] - a0[0]) < 1e-5 * a0[0]
-    assert abs(a1[1] - a0[1]) < 1e-5 * a0[1]
+    say(f"audit {a0} -> {a1}: red {abs(a1[0] - a0[0]) / a0[0]:.2e}, blue {abs(a1[1] - a0[1]) / a0[1]:.2e}, "
+        f"momentum {max(abs(a1[k] - a0[k]) for k in (2, 3, 4)):.2e}")
+    assert abs(a1[0] - a0[0]) < 2e-8 * a0[0]
+    assert abs(a1[1] - a0[1]) < 1e-8 * a0[1]
     assert max(abs(a1[k] - a0[k]) for k in (2, 3, 4)) < 1e-6
+
+
+def test_nonfinite_state_is_reported(torch, orc):
+    """A NaN population (through lbm_set_state) makes lbm_macroscopic's audit
+    return LBM_ERR_NONFINITE instead of totals; a finite state does not."""
+    from paper_1804_08923_amd.lbm import LbmError
+    prob = _periodic_random_problem(9, 7, 5)
+    p, fr, fb, h = random_state(orc, prob, seed=4)
+    st, _, _ = state_to_f32(fr, fb)
+    sim = _sim(prob)
+    sim.set_state(torch.from_numpy(st).cuda(), t=0)
+    assert all(np.isfinite(sim.macroscopic(audit=True)["audit"]))
+    st[5, 77] = np.nan
+    sim.set_state(torch.from_numpy(st).cuda(), t=0)
+    with pytest.raises(LbmError) as ei:
+        sim.macroscopic(audit=True)
+    assert ei.value.code == -4
+    sim.close()
 
 
 def _small_jet(**kw):
@@ -233,6 +276,7 @@ def test_small_jet(torch, orc, steps):
     say(f"  rel Linf {errs}")
     for k, e in errs.items():
         assert e <= 1e-5, k
+    _audit_matches_oracle(sim, fo)
     gr, gb = _gpu_state(sim)
     scale = np.abs(fr + fb).max()
     assert np.abs(gr - fr).max() / scale < 1e-5

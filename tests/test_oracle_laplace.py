@@ -42,3 +42,48 @@ def test_laplace_law_cylinder(orc, gamma, R, tol):
     assert abs(sig - sig_th) / sig_th < tol, (sig, sig_th)
     # spurious currents of the order Table I reports (1e-4 and below)
     assert umax < 1e-4
+
+
+def _octant_droplet_sigma(orc, n, R, steps, W=2.0, A=1e-3, nu=1 / 6):
+    """sigma from Laplace's law in 3-D on one octant of a droplet.
+
+    A red droplet of radius R centred at the corner (-1/2, -1/2, -1/2) of an
+    n^3 jet lattice with a closed inlet: the free-slip walls at x, y, z = -1/2
+    and x, y = n - 1/2 are mirror planes (their equivalence with the mirrored
+    periodic lattice is pinned in test_oracle_jet_bc), so the octant is the
+    droplet of a periodic lattice of period 2n in x and y; the top plane is
+    the convective outlet, far from the droplet, where the fluid stays at rest
+    and which holds the outside pressure.  The pressure is Eq. press with the
+    local alpha_bar; p_in averages r <= R_eff - 3, p_out r >= R_eff + 5 below
+    the top three planes (reading A9), R_eff from the red volume."""
+    prob = Problem(name="octant", nx=n, ny=n, nz=n, bc="jet", rho_r0=1.0, rho_b0=1.0, nu_r=nu, nu_b=nu, A=A,
+                   inlet_D=0.0, inlet_u=0.0, init="jet")
+    p = make_params(prob)
+    fr, fb, h = orc.init_droplet(p, (-0.5, -0.5, -0.5), R, W)
+    z, y, x = (a.ravel() for a in np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"))
+    r = np.sqrt((x + 0.5) ** 2 + (y + 0.5) ** 2 + (z + 0.5) ** 2)
+    out = []
+    done = 0
+    for s in steps:
+        orc.step(p, A, fr, fb, h, done, s - done)
+        done = s
+        rr, rb, u, ph = orc.macroscopic(p, fr, fb)
+        ab = (1 + ph) / 2 * prob.alpha_r + (1 - ph) / 2 * prob.alpha_b
+        pres = (rr + rb) * 9 * (1 - ab) / 19
+        Reff = (3 * 8 * ((1 + ph) / 2).sum() / (4 * np.pi)) ** (1 / 3)
+        dp = pres[r <= Reff - 3].mean() - pres[(r >= Reff + 5) & (z < n - 3)].mean()
+        out.append((dp * Reff / 2, Reff, np.abs(u).max()))
+    return out, 4.0 / 9.0 * A * (3 * nu + 0.5)
+
+
+def test_laplace_law_3d_droplet(orc):
+    """Laplace's law in 3-D, dp = 2 sigma / R, within 2 % of sigma = (4/9) A tau
+    (Eq. sigma) for the static droplet of Sec. III: gamma = 1, tau = 1,
+    A = 1e-3, radius 12, interface width 2.  The octant reaches equilibrium
+    within a few hundred steps; two late measurements must agree (converged)."""
+    res, sig_th = _octant_droplet_sigma(orc, 20, 12.0, (500, 600))
+    (s1, _, _), (s2, Reff, umax) = res
+    assert abs(s2 - s1) < 1e-3 * sig_th, (s1, s2)
+    assert abs(Reff - 12.0) < 0.2
+    assert abs(s2 - sig_th) / sig_th < 0.02, (s2, sig_th)
+    assert umax < 1e-4
