@@ -271,6 +271,21 @@ int lbm_diag_bytes(const lbm_params* p, uint64_t* bytes);
  * parent indices); the result does not depend on the order of the atomics. */
 int lbm_jet_diagnostics(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, int64_t cap);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * diagnostics as lbm_jet_diagnostics, with the work memory taken from a
+ * static array of the library instead of a caller buffer.  The array holds
+ * the work of at most 2^22 nodes (64 MiB + 256 B); it exists once on every
+ * GPU the library runs on, from the first lbm_init on that GPU until the
+ * process ends.  Larger lattices: LBM_ERR_UNSUPPORTED.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the host
+ * copies go straight into stats and volumes.  All calls on one GPU share
+ * that GPU's array, and the last call's contents remain in it: calls that
+ * overlap in time on one GPU (other threads, other streams, other handles)
+ * race and must be serialised by the caller.  Arguments, results and the
+ * host synchronisation are those of lbm_jet_diagnostics. */
+int lbm_jet_diagnostics_static(lbm_handle* h, lbm_jet_stats* stats, int64_t* volumes, int64_t cap);
+
 /* Release the handle (not the caller's buffers).  NULL is accepted. */
 int lbm_destroy(lbm_handle* h);
 

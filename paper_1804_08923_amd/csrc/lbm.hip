@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -13,6 +14,15 @@
 #include "lbm_kernels.h"
 
 using namespace cglbm;
+
+// Work memory of lbm_jet_diagnostics_static (the union-find labels, counts,
+// column marks and fragment volumes of diag_layout) for lattices of up to
+// kStaticDiagNodes nodes, held by the library on every GPU it runs on until
+// the process ends.  Host code reaches it only through the device address
+// hipGetSymbolAddress returns for the current device (g_scratch below).
+constexpr uint64_t kStaticDiagNodes = 1ull << 22;
+constexpr uint64_t kStaticDiagBytes = diag_bytes(kStaticDiagNodes);
+static __device__ __align__(256) unsigned char scratch[kStaticDiagBytes];
 
 // One complete state: population planes (shifted form, or the general form
 // of 54 planes), the recolouring records R, the reference records of the
@@ -32,10 +42,11 @@ struct lbm_handle {
     StateSet ext;       // a caller snapshot that lbm_step_into made current
     int cs;             // current set: 0 or 1 (own), 2 (ext)
     float2* PD;         // (phi, rho - rho_b0) per padded node
-    float* XR;          // rho_r / rho per padded node
+    float* XR;          // tagged minority-colour fraction per padded node
     double* audit;
     void* adjoint;
     hipStream_t stream;
+    int device;         // the HIP device current at lbm_init (its scratch address is g_scratch[device])
     long long t;        // time level of the current state
     int unshifted;      // current buffer holds a general state at the node itself
     dim3 grid_all;      // every interior plane
@@ -54,6 +65,11 @@ struct lbm_handle {
 namespace {
 
 thread_local char g_err[512] = "";
+
+// device address of `scratch` on each device, looked up once per device
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
 
 int fail(int code, const char* fmt, ...)
 {
@@ -187,6 +203,26 @@ struct IntC {
     static constexpr int value = V;
 };
 
+// the device address of the static scratch on device dev (current)
+int scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_ERR_UNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return LBM_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(LBM_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch[dev] = ptr;
+    return LBM_OK;
+}
+
+void* scratch_of(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[dev];
+}
+
 // call f(IntC<bc>, Storage) for the handle's configuration
 template <class F>
 int dispatch(int bc, int storage, F&& f)
@@ -311,6 +347,10 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     if (buf->pop_a == buf->pop_b) return fail(LBM_ERR_INVALID_ARG, "population buffers must differ");
     if (p->init == LBM_INIT_FIELDS && (!rho_r || !rho_b))
         return fail(LBM_ERR_INVALID_ARG, "init from fields needs rho_r and rho_b");
+    int dev = -1;
+    HIP_CHECK(hipGetDevice(&dev));
+    rc = scratch_setup(dev);
+    if (rc != LBM_OK) return rc;
     lbm_handle* H = new (std::nothrow) lbm_handle();
     if (!H) return fail(LBM_ERR_INVALID_ARG, "out of host memory");
     H->p = *p;
@@ -333,6 +373,7 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->audit = buf->audit;
     H->adjoint = buf->adjoint;
     H->stream = (hipStream_t)hip_stream;
+    H->device = dev;
     H->t = 0;
     H->unshifted = 1;
     const unsigned bx = (H->k.plane + BLOCK - 1) / BLOCK;
@@ -737,12 +778,14 @@ int lbm_diag_bytes(const lbm_params* p, uint64_t* bytes)
     return LBM_OK;
 }
 
-int lbm_jet_diagnostics(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
+}  // extern "C"
+
+namespace {
+
+// the diagnostics kernels on work memory w of the handle's lattice; copies the
+// statistics and the first min(cap, n_fragments) volumes to the host
+int diag_run(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
 {
-    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
-    if (!work || !stats) return fail(LBM_ERR_INVALID_ARG, "work and stats are required");
-    if (!aligned(work, 256)) return fail(LBM_ERR_INVALID_ARG, "work must be 256-byte aligned");
-    if (cap < 0 || (cap > 0 && !volumes)) return fail(LBM_ERR_INVALID_ARG, "volumes is NULL with cap > 0");
     const KP k = read_kp(h);
     const DiagWork w = diag_layout(work, k.N);
     int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
@@ -774,12 +817,47 @@ int lbm_jet_diagnostics(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t
     stats->n_fragments = hd.n_fragments;
     const int64_t n = std::min<int64_t>(cap, (int64_t)hd.n_fragments);
     if (n > 0) {
-        std::vector<int> v((size_t)n);
-        HIP_CHECK(hipMemcpyAsync(v.data(), w.volume, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        long long* wide = (long long*)w.label;  // 8 N bytes: labels and counts, free after the collection
+        hipLaunchKernelGGL(k_diag_widen, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, h->stream, w,
+                           (uint32_t)n, wide);
+        LAUNCH_CHECK();
+        HIP_CHECK(hipMemcpyAsync(volumes, wide, (size_t)n * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
         HIP_CHECK(hipStreamSynchronize(h->stream));
-        for (int64_t i = 0; i < n; ++i) volumes[i] = v[(size_t)i];
     }
     return LBM_OK;
+}
+
+int diag_args(lbm_handle* h, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
+{
+    if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (!stats) return fail(LBM_ERR_INVALID_ARG, "stats is required");
+    if (cap < 0 || (cap > 0 && !volumes)) return fail(LBM_ERR_INVALID_ARG, "volumes is NULL with cap > 0");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_jet_diagnostics(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
+{
+    const int rc = diag_args(h, stats, volumes, cap);
+    if (rc != LBM_OK) return rc;
+    if (!work) return fail(LBM_ERR_INVALID_ARG, "work is required");
+    if (!aligned(work, 256)) return fail(LBM_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    return diag_run(h, work, stats, volumes, cap);
+}
+
+int lbm_jet_diagnostics_static(lbm_handle* h, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
+{
+    const int rc = diag_args(h, stats, volumes, cap);
+    if (rc != LBM_OK) return rc;
+    if ((uint64_t)h->k.N > kStaticDiagNodes)
+        return fail(LBM_ERR_UNSUPPORTED, "%u nodes exceed the %llu nodes of the static diagnostics scratch", h->k.N,
+                    (unsigned long long)kStaticDiagNodes);
+    void* ptr = scratch_of(h->device);
+    if (!ptr) return fail(LBM_ERR_STATE, "no scratch address for device %d", h->device);
+    return diag_run(h, ptr, stats, volumes, cap);
 }
 
 const char* lbm_status_string(int status)

@@ -41,7 +41,7 @@ struct DiagWork {
     int* volume;
 };
 
-inline uint64_t diag_bytes(uint64_t N) { return 256 + 4 * 4 * N; }
+constexpr uint64_t diag_bytes(uint64_t N) { return 256 + 4 * 4 * N; }
 
 inline DiagWork diag_layout(void* base, uint64_t N)
 {
@@ -190,6 +190,14 @@ __global__ __launch_bounds__(BLOCK) void k_diag_collect(KP k, DiagWork w)
         const unsigned int slot = atomicAdd(&w.hdr->n_fragments, 1u);
         w.volume[slot] = w.count[i];
     }
+}
+
+// 6. the first n fragment volumes widened to int64 into out (the label and
+// count arrays, free once the volumes are collected), for the host copy
+__global__ __launch_bounds__(BLOCK) void k_diag_widen(DiagWork w, uint32_t n, long long* __restrict__ out)
+{
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) out[i] = (long long)w.volume[i];
 }
 
 }  // namespace cglbm

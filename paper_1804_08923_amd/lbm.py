@@ -60,8 +60,8 @@ class lbm_buffers(C.Structure):
 
 EXPORTS = ("lbm_query_sizes", "lbm_init", "lbm_step", "lbm_macroscopic", "lbm_get_state", "lbm_set_state",
            "lbm_time", "lbm_step_into", "lbm_snapshot_save", "lbm_snapshot_load", "lbm_adjoint_step",
-           "lbm_adjoint_step_snapshot", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
-           "lbm_profile_read", "lbm_destroy", "lbm_status_string", "lbm_last_error")
+           "lbm_adjoint_step_snapshot", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_jet_diagnostics_static",
+           "lbm_profile", "lbm_profile_read", "lbm_destroy", "lbm_status_string", "lbm_last_error")
 
 _lib = None
 
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_snapshot_load.argtypes = [vp, vp, i64]
     lib.lbm_diag_bytes.argtypes = [C.POINTER(lbm_params), C.POINTER(C.c_uint64)]
     lib.lbm_jet_diagnostics.argtypes = [vp, vp, C.POINTER(lbm_jet_stats), C.POINTER(C.c_int64), C.c_int64]
+    lib.lbm_jet_diagnostics_static.argtypes = [vp, C.POINTER(lbm_jet_stats), C.POINTER(C.c_int64), C.c_int64]
     lib.lbm_profile.argtypes = [vp, C.c_int]
     lib.lbm_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.lbm_destroy.argtypes = [vp]
@@ -98,8 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_query_sizes", "lbm_init", "lbm_step", "lbm_macroscopic", "lbm_get_state",
                  "lbm_set_state", "lbm_step_into", "lbm_snapshot_save", "lbm_snapshot_load", "lbm_adjoint_step",
-                 "lbm_adjoint_step_snapshot", "lbm_diag_bytes", "lbm_jet_diagnostics", "lbm_profile",
-                 "lbm_profile_read", "lbm_destroy"):
+                 "lbm_adjoint_step_snapshot", "lbm_diag_bytes", "lbm_jet_diagnostics",
+                 "lbm_jet_diagnostics_static", "lbm_profile", "lbm_profile_read", "lbm_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -280,6 +281,19 @@ class LBM:
             _check(self.lib, self.lib.lbm_jet_diagnostics(self.h, self._diag_work.data_ptr(), C.byref(st), vol,
                                                           cap))
         n = min(cap, st.n_fragments)
+        v = np.sort(np.frombuffer(vol, dtype=np.int64, count=n))[::-1].copy()
+        return {k: int(getattr(st, k)) for k, _ in lbm_jet_stats._fields_}, v
+
+    def jet_diagnostics_static(self, cap: int):
+        """jet_diagnostics through lbm_jet_diagnostics_static (the library's
+        static work memory; no device buffer is allocated): the four
+        statistics and the first min(cap, n_fragments) fragment volumes,
+        sorted in descending order."""
+        import numpy as np
+        st = lbm_jet_stats()
+        vol = (C.c_int64 * max(int(cap), 1))()
+        _check(self.lib, self.lib.lbm_jet_diagnostics_static(self.h, C.byref(st), vol, int(cap)))
+        n = min(int(cap), st.n_fragments)
         v = np.sort(np.frombuffer(vol, dtype=np.int64, count=n))[::-1].copy()
         return {k: int(getattr(st, k)) for k, _ in lbm_jet_stats._fields_}, v
 

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(lbm.EXPORTS)
-    assert len(names) == 19
+    assert len(names) == 20
 
 
 def test_query_sizes(lib):
@@ -94,6 +94,7 @@ def test_snapshot_entry_points_reject_null_handles(lib):
     assert lib.lbm_snapshot_save(None, None) == -5
     assert lib.lbm_snapshot_load(None, None, 0) == -5
     assert lib.lbm_adjoint_step_snapshot(None, None, 0, None, None, None, None) == -5
+    assert lib.lbm_jet_diagnostics_static(None, None, None, 0) == -5
 
 
 def test_status_strings(lib):
