@@ -713,13 +713,13 @@ int lbm_adjoint_step_snapshot(lbm_handle* h, const void* snap_t, int64_t t, cons
         if (BC == LBM_BC_JET) {
             const dim3 gi(h->grid_dtiles.x, (unsigned)(h->p.nz - 1));
             const dim3 go((unsigned)((h->k.plane + OBLOCK - 1) / OBLOCK));
-            hipLaunchKernelGGL((k_density<BC, S>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k, w.MOM);
+            hipLaunchKernelGGL((k_density<BC, S, true>), gi, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k, w.MOM);
             LAUNCH_CHECK();
             hipLaunchKernelGGL((k_outlet_density<S>), go, dim3(OBLOCK), 0, h->stream, src, h->PD, h->XR, s.hist,
                                w.ST, k, w.MOM);
         } else {
-            hipLaunchKernelGGL((k_density<BC, S>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD, h->XR, k,
-                               w.MOM);
+            hipLaunchKernelGGL((k_density<BC, S, true>), h->grid_dtiles, dim3(DBLOCK), 0, h->stream, src, h->PD,
+                               h->XR, k, w.MOM);
         }
         LAUNCH_CHECK();
         return LBM_OK;
