@@ -112,3 +112,12 @@ def separable_state_fields(prob, seed, amp_u=0.02):
         X, Y, Z = wave(0, 2), wave(1, 2), wave(2, 2)
         u[:, c] = (amp_u * Z[:, None, None] * Y[None, :, None] * X[None, None, :]).astype(np.float32).ravel()
     return rho_r, rho_b, u
+
+
+def droplet_profile(n, R, W, center=None):
+    """The order parameter of the static droplet of Sec. III on an n^3
+    lattice, phi = -tanh(2 (r - R) / W) (node order, x fastest)."""
+    c = (n - 1) / 2.0 if center is None else center
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2).ravel()
+    return -np.tanh(2.0 * (r - R) / W)

@@ -87,3 +87,64 @@ def test_laplace_law_3d_droplet(orc):
     assert abs(Reff - 12.0) < 0.2
     assert abs(s2 - sig_th) / sig_th < 0.02, (s2, sig_th)
     assert umax < 1e-4
+
+
+def balanced_densities(prob, phi):
+    """Colour densities with the order parameter phi (Eq. order) whose pressure
+    (Eq. press, p = rho 9 (1 - alpha_bar)/19 with alpha_bar linear in phi) is the
+    bulk value everywhere: rho_k = rho_k0 s (1 +- phi)/2 with the scale s that
+    makes rho (1 - alpha_bar) = rho_b0 (1 - alpha_b); s = 1 in the pure phases.
+    (READING for the static droplets at gamma >= 100: the printed tanh
+    densities put (gamma + 2 + 1/gamma)/4 times the bulk pressure into the
+    interface, and the currents that start drives grow to O(0.1).)"""
+    ab = prob.alpha_r * (1 + phi) / 2 + prob.alpha_b * (1 - phi) / 2
+    rho_mix = prob.rho_r0 * (1 + phi) / 2 + prob.rho_b0 * (1 - phi) / 2
+    s = prob.rho_b0 * (1 - prob.alpha_b) / (rho_mix * (1 - ab))
+    return prob.rho_r0 * s * (1 + phi) / 2, prob.rho_b0 * s * (1 - phi) / 2
+
+
+def test_balanced_start_has_uniform_pressure(orc):
+    """The pressure-balanced start: phi is the tanh profile, the pressure of
+    Eq. press is uniform, and the oracle's state reproduces both."""
+    from synth import droplet_profile
+    for gamma in (10.0, 100.0, 1000.0):
+        prob = Problem(name="bal", nx=12, ny=12, nz=12, bc="periodic", rho_r0=1.0, rho_b0=1.0 / gamma,
+                       nu_r=1 / 6, nu_b=1 / 6, A=8e-4)
+        p = make_params(prob)
+        phi = droplet_profile(12, 3.0, 4.0)
+        rr, rb = balanced_densities(prob, phi)
+        fr, fb, h = orc.init_fields(p, rr, rb)
+        a, b, u, ph = orc.macroscopic(p, fr, fb)
+        assert np.abs(ph - phi).max() < 1e-12
+        ab = (1 + ph) / 2 * prob.alpha_r + (1 - ph) / 2 * prob.alpha_b
+        pres = (a + b) * 9 * (1 - ab) / 19
+        assert np.abs(pres / pres.mean() - 1).max() < 1e-12
+        # the printed tanh densities are far from uniform pressure there (the
+        # peak (gamma + 2 + 1/gamma)/4 sits at phi = 0, which the 12^3
+        # lattice samples only approximately)
+        rr2, rb2 = prob.rho_r0 * (1 + phi) / 2, prob.rho_b0 * (1 - phi) / 2
+        p2 = (rr2 + rb2) * 9 * (1 - ab) / 19
+        assert p2.max() / p2.min() > 1 + 0.3 * ((gamma + 2 + 1 / gamma) / 4 - 1)
+
+
+def test_balanced_start_survives_at_gamma_100(orc):
+    """The droplet at gamma = 100 (32^3, R = 8, W = 4, A = 8e-4): from the
+    tanh densities the FP64 oracle's currents grow to O(0.1) within 60 steps;
+    from the balanced start they stay finite and decay."""
+    from synth import droplet_profile
+    prob = Problem(name="bal100", nx=32, ny=32, nz=32, bc="periodic", rho_r0=1.0, rho_b0=0.01,
+                   nu_r=1 / 6, nu_b=1 / 6, A=8e-4)
+    p = make_params(prob)
+    phi = droplet_profile(32, 8.0, 4.0)
+    rr, rb = balanced_densities(prob, phi)
+    fr, fb, h = orc.init_fields(p, rr, rb)
+    orc.step(p, prob.A, fr, fb, h, 0, 20)
+    u20 = np.abs(orc.macroscopic(p, fr, fb)[2]).max()
+    orc.step(p, prob.A, fr, fb, h, 20, 130)
+    u150 = np.abs(orc.macroscopic(p, fr, fb)[2]).max()
+    assert np.isfinite(u150) and u150 < 0.5 * u20, (u20, u150)
+    fr, fb, h = orc.init_fields(p, prob.rho_r0 * (1 + phi) / 2, prob.rho_b0 * (1 - phi) / 2)
+    with np.errstate(all="ignore"):
+        orc.step(p, prob.A, fr, fb, h, 0, 60)
+        u = orc.macroscopic(p, fr, fb)[2]
+    assert not np.isfinite(u).all() or np.abs(u).max() > 10 * u150, (np.abs(u).max(), u150)
