@@ -17,10 +17,13 @@ stdout.  Thread count: OMP_NUM_THREADS.
 
     python tests/golden/make_jet_oracle_fields.py --sample jet-128x128x512 --steps 100,1000
 
-writes the sample the GPU comparison reads, tests/golden/cache_ship/
-<workload>_oracle_sample.npz: the fields rho, u, phi at every node with even
-x and even y (all z), per step, with the maxima of |rho|, |u|, |phi| over the
-whole lattice (the denominators of the relative errors).
+writes the sample the GPU comparison reads, tests/golden/jet_sample/
+<workload>_oracle_sample.npz: the fields rho, u, phi (FP32) per step at the
+nodes listed in ``idx`` (node order), with the maxima of |rho|, |u|, |phi|
+over the whole lattice (the denominators of the relative errors) and the
+FP64 totals.  The sample: every node with x and y multiples of 8 (all z),
+plus, around the jet column (|x - cx|, |y - cy| <= 24, z < 160, where the
+interface is during the first 1000 steps), every node with even x and y.
 """
 from __future__ import annotations
 
@@ -85,26 +88,35 @@ def main() -> int:
 
 def write_sample(workload: str, marks, cache: str) -> int:
     prob = WORKLOADS[workload]()
-    nx, ny, nz = prob.nx, prob.ny, prob.nz
-    out = {"stride_xy": np.int64(2), "steps": np.array(marks, np.int64)}
+    idx = sample_nodes(prob)
+    out = {"idx": idx.astype(np.int32), "steps": np.array(marks, np.int64)}
     for m in marks:
         with np.load(os.path.join(cache, f"{workload}_oracle_t{m}.npz")) as f:
             rho = (f["rho_r"].astype(np.float64) + f["rho_b"].astype(np.float64))
-            u = f["u"].reshape(nz, ny, nx, 3)
+            u = f["u"]
             phi = f["phi"]
-            sel = (slice(None), slice(0, None, 2), slice(0, None, 2))
-            out[f"rho_{m}"] = rho.reshape(nz, ny, nx)[sel].astype(np.float32).ravel()
-            out[f"u_{m}"] = u[sel].reshape(-1, 3)
-            out[f"phi_{m}"] = phi.reshape(nz, ny, nx)[sel].ravel()
-            out[f"max_{m}"] = np.array([np.abs(rho).max(), np.linalg.norm(f["u"].astype(np.float64), axis=1).max(),
+            out[f"rho_{m}"] = rho[idx].astype(np.float32)
+            out[f"u_{m}"] = u[idx]
+            out[f"phi_{m}"] = phi[idx]
+            out[f"max_{m}"] = np.array([np.abs(rho).max(), np.linalg.norm(u.astype(np.float64), axis=1).max(),
                                         np.abs(phi).max()])
             out[f"totals_{m}"] = f["totals"]
-    ship = os.path.join(HERE, "cache_ship")
+    ship = os.path.join(HERE, "jet_sample")
     os.makedirs(ship, exist_ok=True)
     path = os.path.join(ship, f"{workload}_oracle_sample.npz")
-    np.savez(path, **out)
-    print(f"wrote {path}", flush=True)
+    np.savez_compressed(path, **out)
+    print(f"wrote {path} ({idx.size} nodes)", flush=True)
     return 0
+
+
+def sample_nodes(prob) -> np.ndarray:
+    """Node indices of the shipped sample (see the module docstring)."""
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    coarse = (x % 8 == 0) & (y % 8 == 0)
+    near = ((np.abs(x - prob.inlet_cx) <= 24) & (np.abs(y - prob.inlet_cy) <= 24) & (z < 160)
+            & (x % 2 == 0) & (y % 2 == 0))
+    return np.flatnonzero((coarse | near).ravel()).astype(np.int64)
 
 
 if __name__ == "__main__":
