@@ -6,11 +6,11 @@ u = 0.05, gamma = 2, eta = 0.01, Re = 1e6, We = 1e3, Fr = 10, 1 % seeded radial
 inlet noise), synthetic, populations resident in HBM.  A step is one full time
 step of the method (density pass + fused collide-perturb-recolour-stream kernel
 with the jet boundaries).  The jet is first developed for `--warmup` steps
-(default 2000, outside the timed region); then `--steps` steps are timed with
-HIP events on the library's stream, with no instrumentation inside the timed
-region.  A separate profiled pass right after it (the library's per-kernel
-events) gives the per-kernel durations.  Prints ONE JSON line on stdout;
-progress goes to stderr.
+(default 2000, outside the timed region); then `--steps` steps (default 2000)
+are timed with HIP events on the library's stream, with no instrumentation
+inside the timed region.  A separate profiled pass right after it (the
+library's per-kernel events) gives the per-kernel durations.  Prints ONE JSON
+line on stdout; progress goes to stderr.
 
 value = MLUPS of the FP32-storage step (nodes x steps / s / 1e6).
 roofline = the fused kernel's algorithmic bytes per launch / its average
@@ -234,7 +234,7 @@ def cpu_baseline(prob, nz_sample=8, budget_s=10.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--workload", default="jet-256x256x1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")

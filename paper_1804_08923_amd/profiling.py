@@ -2,15 +2,15 @@
 
     python -m paper_1804_08923_amd.profiling trace <results.db>
     python -m paper_1804_08923_amd.profiling pmc <results.db>
-    python -m paper_1804_08923_amd.profiling traffic <fetch.db> <write.db> <storage> <kernel> <out.json>
+    python -m paper_1804_08923_amd.profiling traffic <fetch.db> <write.db> <key> <kernel> <out.json>
 
 ``trace`` prints per-kernel call counts and durations; ``pmc`` prints the
 per-dispatch average and maximum of every collected counter per kernel.
 ``traffic`` turns a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch) of a
 command that also made a 1 GiB device copy into HBM bytes per launch of
 <kernel>: each counter is scaled by 1 GiB over what it read for the copy's
-largest dispatch, and the result is stored under <storage> in <out.json>
-together with a hash of the kernel sources it was measured on.
+largest dispatch, and the result is stored under <key> (workload/storage) in
+<out.json> together with a hash of the kernel sources it was measured on.
 """
 from __future__ import annotations
 
@@ -102,7 +102,7 @@ def main(argv):
         print(trace_summary(argv[2]) if argv[1] == "trace" else pmc_summary(argv[2]))
         return 0
     if len(argv) == 7 and argv[1] == "traffic":
-        _, _, fdb, wdb, storage, kernel, out = argv
+        _, _, fdb, wdb, key, kernel, out = argv
         t = traffic(fdb, wdb, kernel)
         t["kernel"] = kernel
         t["kernel_hash"] = kernel_source_hash()
@@ -110,7 +110,7 @@ def main(argv):
         if os.path.exists(out):
             with open(out) as fh:
                 allt = json.load(fh)
-        allt[storage] = t
+        allt[key] = t
         with open(out, "w") as fh:
             json.dump(allt, fh, indent=1)
         print(json.dumps(t, indent=1))
