@@ -138,8 +138,7 @@ def test_table1_droplet(torch, row, balanced):
         assert umax <= 4.0 * umax_tab
 
 
-@pytest.mark.xfail(reason="at gamma >= 100 the interface carries spurious currents 20-130x the printed ones "
-                          "(the printed gamma = 1 value matches this path at the A = 0.01 of the text)",
+@pytest.mark.xfail(reason="at gamma >= 100 the interface carries spurious currents 20-130x the printed ones",
                    strict=True)
 @pytest.mark.parametrize("row", [2, 3])
 def test_table1_spurious_velocity_high_gamma(torch, row):
