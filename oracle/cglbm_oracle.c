@@ -19,8 +19,12 @@
  *
  * Parity status: every function here is pinned by a test in tests/ against
  * values the paper prints (Appendix A matrices) or against closed forms,
- * invariants and special cases, except the jet boundary rules (parity
- * unpinned by the paper: pinned only by mass/momentum budgets).
+ * invariants and special cases.  The jet boundary rules, which the paper
+ * gives only in words, are pinned by consequences (tests/test_oracle_jet_bc.py):
+ * the free-slip walls against a mirrored periodic lattice (method of images),
+ * the inflow against closed-form moments of the inlet equilibrium, fixed
+ * points with a closed or resting inlet, the outflow rule at t + 1, and the
+ * symmetries of a centred jet.
  */
 #include "cglbm_oracle.h"
 
