@@ -1166,6 +1166,24 @@ __device__ __forceinline__ void ghost_pair_t(const KP& k, const Node& nd, typena
     }
 }
 
+// The x-wall ghost slots that no pull reads (directions that do not point back
+// into the lattice) are written too, with zero, so that every cache line of a
+// population plane is written whole: a partly written line costs the memory a
+// read-modify-write.  A probe of the fused kernel's access pattern on the
+// 256x256x1024 lattice: 3.40 ms with the unread slots left alone, 3.16 ms
+// with every slot of the row written.
+template <class S, int J = 0>
+__device__ __forceinline__ void ghost_zero_x(const KP& k, uint32_t n, typename S::T* __restrict__ dst, bool xl,
+                                             bool xh)
+{
+    if constexpr (J < Q) {
+        constexpr int cx = kCX[J];
+        if (cx <= 0 && xl) stp(dst + (size_t)J * k.NP, n - 1u, S::enc(0.f));
+        if (cx >= 0 && xh) stp(dst + (size_t)J * k.NP, n + 1u, S::enc(0.f));
+        ghost_zero_x<S, J + 1>(k, n, dst, xl, xh);
+    }
+}
+
 #define CGLBM_GP(I) \
     case I: ghost_pair_t<BC, S, I>(k, nd, dst, vp, vm, xl, xh, yz_edge); break;
 // dispatch on the (unrolled, constant) pair index
@@ -1370,6 +1388,7 @@ __device__ __forceinline__ void collide_store(const KP& k, const Node& nd, const
         stpl(dst + (size_t)(i + 1) * N, k.NP, n, S::enc(dm));
         ghost_pair<BC, S>(i, k, nd, dst, dp, dm, xl, xh, yz_edge);
     }
+    if (!yz_edge && (xl || xh)) ghost_zero_x<S>(k, n, dst, xl, xh);
 }
 
 
