@@ -7,12 +7,19 @@ fields are made once by tests/golden/make_jet_oracle_fields.py (oracle only)
 and shipped as a sample (tests/golden/jet_sample/): every node with x and y
 multiples of 8, plus every node with even x and y around the jet column for
 z < 160, with the maxima of |rho|, |u| and |phi| over the whole lattice as
-the denominators.  The GPU runs the same jet
-from the same all-blue start in each storage form; the table of relative
-L-inf errors (over the sample) is printed.  Bars: FP32 within 1e-5 on rho
-and 1e-4 on u and phi; the 16-bit forms are reported against the 1e-3 u_max
-target without an assertion (test_gpu_storage holds them to it at small
-size).  Skipped when the cached sample is absent.
+the denominators.  The GPU runs the same jet from the same all-blue start in
+each storage form; the table of relative L-inf errors (over the sample) is
+printed.
+
+Bars (FP32): step 100, rho 1e-6, u 1e-5, phi 2e-6 (measured 1.7e-7, 1.1e-6,
+3.8e-7); step 1000, 1e-4 on each field (measured 1.1e-5, 1.5e-5, 4.1e-5).
+The FP32 trajectory parts from the FP64 one as the jet amplifies rounding
+(a factor of about 60 between steps 100 and 1000); the step-1000 bar is a
+regression bound, since the oracle's own FP32 floor at that step would take
+another six hours of host time.  The equilibrium-referenced FP16 form is held
+to the 1e-3 u_max velocity bound at both steps; the other 16-bit forms miss
+it and are reported (test_gpu_storage holds them to it as strict expected
+failures at small size).  Skipped when the sample is absent.
 """
 import os
 
@@ -66,6 +73,9 @@ def test_jet128_error_table(torch):
                 f"red mass {e['mass_r']:.2e}  (u_max {mx[1]:.3e})")
         sim.close()
         torch.cuda.empty_cache()
+    bars = {100: (1e-6, 1e-5, 2e-6), 1000: (1e-4, 1e-4, 1e-4)}
     for m in marks:
         e = table[("fp32", m)]
-        assert e["rho"] <= 1e-5 and e["u"] <= 1e-4 and e["phi"] <= 1e-4, (m, e)
+        b = bars[m]
+        assert e["rho"] <= b[0] and e["u"] <= b[1] and e["phi"] <= b[2], (m, e)
+        assert table[("fp16eq", m)]["u"] <= 1e-3, (m, table[("fp16eq", m)])
