@@ -46,21 +46,40 @@
 #define R_SQRT(x) sqrt(x)
 #endif
 
+/* OR_Q19 builds the same scheme on the D3Q19 subset of the velocity set (the
+ * reduced lattice the paper suggests in Sec. II and Sec. IV B as the way to
+ * cut the cost, without giving its coefficients).  Its constants are derived
+ * below so that every moment the D3Q27 coefficients fix is kept (READING, one
+ * note per constant). */
+#if defined(OR_Q19)
+#define Q 19
+#else
 #define Q 27
+#endif
 
-/* ---- lattice (Eq. velVec; weights below it) ----------------------------- */
-static const int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1,
+/* ---- lattice (Eq. velVec; weights below it) -----------------------------
+ * The 27 directions in the paper's order; the first 19 (rest, faces, edges)
+ * are the D3Q19 subset. */
+static const int CX[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1,
                           1, -1, 1, -1, 1, -1, -1, 1};
-static const int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 1, -1, 1, -1, 0, 0, 0, 0,
+static const int CY[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 1, -1, 1, -1, 0, 0, 0, 0,
                           1, -1, 1, -1, -1, 1, 1, -1};
-static const int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+static const int CZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
                           1, -1, -1, 1, 1, -1, 1, -1};
 
 static int csq(int i) { return CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]; }
 
-/* D3Q27 weights by |c|^2 = 0, 1, 2, 3 */
+/* D3Q27 weights by |c|^2 = 0, 1, 2, 3; D3Q19: the standard weights 1/3,
+ * 1/18, 1/36, which keep sum w c c = delta/3 and an isotropic fourth moment */
 static double weight(int i)
 {
+#if defined(OR_Q19)
+    switch (csq(i)) {
+    case 0: return 1.0 / 3.0;
+    case 1: return 1.0 / 18.0;
+    default: return 1.0 / 36.0;
+    }
+#endif
     switch (csq(i)) {
     case 0: return 8.0 / 27.0;
     case 1: return 2.0 / 27.0;
@@ -69,9 +88,15 @@ static double weight(int i)
     }
 }
 
-/* perturbation constants B_i (Eq. B_i), c = 1 */
+/* perturbation constants B_i (Eq. B_i), c = 1.  On D3Q27 they are B_i = w_i
+ * for i > 0 and B_0 = w_0 - 2/3, so that sum B_i = c_s^2 = 1/3 (the operator
+ * moves no mass) and sum B_i c c = delta/3.  READING (D3Q19): the same two
+ * rules on D3Q19, B_0 = 1/3 - 2/3 = -1/3, B_i = w_i. */
 static double bcoef(int i)
 {
+#if defined(OR_Q19)
+    return csq(i) == 0 ? -1.0 / 3.0 : weight(i);
+#endif
     switch (csq(i)) {
     case 0: return -10.0 / 27.0;
     case 1: return 2.0 / 27.0;
@@ -127,11 +152,20 @@ static or_real moment_poly(int j, or_real X, or_real Y, or_real Z)
     }
 }
 
+/* Row j of the basis in use.  READING (D3Q19): the 19 rows of Eq. momentSet
+ * that are not identically zero or dependent on the D3Q19 velocities, that is
+ * all but XYZ and the rows of degree 4 and above in which all three
+ * components appear: 1, X, Y, Z, the six second-order rows, the six
+ * third-order rows without XYZ, and the three rows X2Y2 +/- ... .  Their span is
+ * closed under the shift c -> c - u, so N(u) is again unit lower triangular
+ * and exact. */
+static int basis_row(int j) { return (Q == 19 && j >= 16) ? j + 1 : j; }
+
 void or_moment_matrix(const or_real* u3, or_real* T)
 {
     for (int j = 0; j < Q; ++j)
         for (int i = 0; i < Q; ++i)
-            T[j * Q + i] = moment_poly(j, (or_real)CX[i] - u3[0], (or_real)CY[i] - u3[1],
+            T[j * Q + i] = moment_poly(basis_row(j), (or_real)CX[i] - u3[0], (or_real)CY[i] - u3[1],
                                        (or_real)CZ[i] - u3[2]);
 }
 
@@ -194,7 +228,7 @@ static void ensure_M(void)
                 for (int i = 0; i < Q; ++i) {
                     double X = CX[i], Y = CY[i], Z = CZ[i];
                     /* evaluate the same polynomial rows in double */
-                    or_real v = moment_poly(j, (or_real)X, (or_real)Y, (or_real)Z);
+                    or_real v = moment_poly(basis_row(j), (or_real)X, (or_real)Y, (or_real)Z);
                     a[j * Q + i] = (double)RE(v);
                 }
             memcpy(g_M, a, sizeof(a));
@@ -259,9 +293,19 @@ void or_shift_matrix(const or_real* u3, or_real* N)
 
 /* ---- per-node operators -------------------------------------------------- */
 
-/* varphi_i(alpha_bar), Eq. varphi_ik */
+/* varphi_i(alpha_bar), Eq. varphi_ik.  On D3Q27 the moving coefficients are
+ * w_i (1 - alpha) / (1 - w_0), so that sum varphi_i = 1 and
+ * sum varphi_i c c = (9/19)(1 - alpha) delta.  READING (D3Q19): the same rule,
+ * (1 - alpha)/12 on faces and (1 - alpha)/24 on edges, which gives the colour
+ * a sound speed squared of (1 - alpha)/2. */
 void or_phi_coeffs(or_real ab, or_real* ph)
 {
+#if defined(OR_Q19)
+    for (int i = 0; i < Q; ++i)
+        ph[i] = csq(i) == 0 ? ab : csq(i) == 1 ? ((or_real)1 - ab) / (or_real)12
+                                                : ((or_real)1 - ab) / (or_real)24;
+    return;
+#endif
     for (int i = 0; i < Q; ++i) {
         switch (csq(i)) {
         case 0: ph[i] = ab; break;
@@ -288,7 +332,12 @@ void or_gradient(const or_real* chi27, or_real* g3)
 }
 
 /* enhanced equilibrium, Eq. EES with Phi_i of Eq. Phi and the tensor G
- * defined below Eq. order; c = 1. */
+ * defined below Eq. order; c = 1.  The D3Q27 Phi_i have sum Phi_i = 0,
+ * sum Phi_i c = 0 and sum Phi_i c c = nu_bar [u grad rho + grad rho u +
+ * (u . grad rho) I].  READING (D3Q19): Phi_0 = -3 nu_bar u . grad rho as on
+ * D3Q27 and Phi_i = m_i nu_bar G' : c_i c_i with G' = 6 G (the symmetric
+ * product over 8), m = 2 on faces and 1 on edges: the only such weights
+ * with an isotropic fourth moment, and they give the same three moments. */
 void or_equilibrium(or_real rho, const or_real* u, or_real ab, or_real nub,
                     const or_real* grho, or_real* feq)
 {
@@ -298,7 +347,7 @@ void or_equilibrium(or_real rho, const or_real* u, or_real ab, or_real nub,
     /* G = [u (x) grad rho + (u (x) grad rho)^T] / 48 */
     or_real G[3][3];
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) G[a][b] = (u[a] * grho[b] + u[b] * grho[a]) / (or_real)48;
+        for (int b = 0; b < 3; ++b) G[a][b] = (u[a] * grho[b] + u[b] * grho[a]) / (or_real)(Q == 19 ? 8 : 48);
     or_real udr = u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2];
     for (int i = 0; i < Q; ++i) {
         or_real c[3] = {(or_real)CX[i], (or_real)CY[i], (or_real)CZ[i]};
@@ -313,7 +362,7 @@ void or_equilibrium(or_real rho, const or_real* u, or_real ab, or_real nub,
             or_real GCC = 0;
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) GCC += G[a][b] * c[a] * c[b];
-            double m = (k == 1) ? 16.0 : (k == 2) ? 4.0 : 1.0;
+            double m = (Q == 19) ? ((k == 1) ? 2.0 : 1.0) : (k == 1) ? 16.0 : (k == 2) ? 4.0 : 1.0;
             Phi = (or_real)m * nub * GCC;
         }
         feq[i] = rho * (ph[i] + (or_real)weight(i) * poly) + Phi;
@@ -368,7 +417,9 @@ static void lower_solve(const or_real* N, const or_real* b, or_real* x)
 
 /* GMRT single-phase collision plus forcing (Eqs. scoll and ketF):
  *   fdag = f - M^-1 N^-1 K N M (f - feq) + M^-1 N^-1 (I - K/2) N M F'
- * with K = diag[s0, s1 x3, s2nu x5, s2b, s3 x7, s4 x6, s5 x3, s6]. */
+ * with K = diag[s0, s1 x3, s2nu x5, s2b, s3 x7, s4 x6, s5 x3, s6].
+ * READING (D3Q19): K = diag[s0, s1 x3, s2nu x5, s2b, s3 x6, s4 x3], the
+ * rates of the rows kept from D3Q27; s5 and s6 have no rows. */
 void or_collide(const or_params* p, const or_real* f, const or_real* feq, const or_real* Fp,
                 const or_real* u, or_real s2nu, or_real* fdag)
 {
@@ -380,15 +431,20 @@ void or_collide(const or_params* p, const or_real* f, const or_real* feq, const 
         for (int i = 0; i < Q * Q; ++i) N[i] = 0;
         for (int i = 0; i < Q; ++i) N[i * Q + i] = 1;
     }
-    or_real K[Q];
+    or_real K[27];
     K[0] = (or_real)p->rates[0];
     for (int j = 1; j <= 3; ++j) K[j] = (or_real)p->rates[1];
     for (int j = 4; j <= 8; ++j) K[j] = s2nu;
     K[9] = (or_real)p->rates[3];
+#if defined(OR_Q19)
+    for (int j = 10; j <= 15; ++j) K[j] = (or_real)p->rates[4];
+    for (int j = 16; j <= 18; ++j) K[j] = (or_real)p->rates[5];
+#else
     for (int j = 10; j <= 16; ++j) K[j] = (or_real)p->rates[4];
     for (int j = 17; j <= 22; ++j) K[j] = (or_real)p->rates[5];
     for (int j = 23; j <= 25; ++j) K[j] = (or_real)p->rates[6];
     K[26] = (or_real)p->rates[7];
+#endif
 
     or_real dif[Q], a[Q], b[Q], c[Q], d[Q], e[Q];
     /* collision term */

@@ -9,15 +9,19 @@
  * and the CPU-baseline leg of bench.py may load it.  It shares no code,
  * tables or headers with the GPU path.
  *
- * One source file is compiled three times:
+ * One source file is compiled four times:
  *   liboracle.so      real = double          (the FP64 oracle)
  *   liboracle_cs.so   real = double complex  (complex-step tangent-linear)
  *   liboracle_f32.so  real = float           (FP32 floor of the plain scheme)
+ *   liboracle_q19.so  real = double, on the D3Q19 subset of the velocity set
+ *                     (the reduced lattice of Sec. II; Q = 19 below)
  * Every array argument typed `or_real` takes that build's element type.
  *
  * Population arrays are structure-of-arrays: element (i, node) sits at
- * i*N + node with node = (z*ny + y)*nx + x, i = 0..26 in the order of the
- * paper's velocity set (Eq. velVec).
+ * i*N + node with node = (z*ny + y)*nx + x, i = 0..Q-1 in the order of the
+ * paper's velocity set (Eq. velVec); Q = 27, or 19 (rest, faces, edges: the
+ * first 19 of that order) in the D3Q19 build.  Sizes written 27 below are Q
+ * in the D3Q19 build.
  */
 #ifndef CGLBM_ORACLE_H
 #define CGLBM_ORACLE_H

@@ -8,7 +8,10 @@ same C source are exposed:
   is the tangent-linear (directional derivative) of the FP64 scheme to
   round-off (Squire and Trapp 1998, complex-step differentiation);
 * ``"f32"`` -- the same plain scheme in single precision, used to measure the
-  FP32 round-off floor of the unmodified populations.
+  FP32 round-off floor of the unmodified populations;
+* ``"q19"`` -- the FP64 scheme on the D3Q19 subset of the velocity set (the
+  reduced lattice of Sec. II, with the derived coefficients noted in the C
+  source); its arrays have 19 directions (``Oracle.Q``).
 """
 from __future__ import annotations
 
@@ -25,8 +28,10 @@ _LIBS = {
     "f64": ("liboracle.so", []),
     "cs": ("liboracle_cs.so", ["-DOR_COMPLEX"]),
     "f32": ("liboracle_f32.so", ["-DOR_FLOAT"]),
+    "q19": ("liboracle_q19.so", ["-DOR_Q19"]),
 }
-_DTYPES = {"f64": np.float64, "cs": np.complex128, "f32": np.float32}
+_DTYPES = {"f64": np.float64, "cs": np.complex128, "f32": np.float32, "q19": np.float64}
+_NQ = {"f64": 27, "cs": 27, "f32": 27, "q19": 19}
 _lock = threading.Lock()
 _cache: dict = {}
 
@@ -101,6 +106,7 @@ class Oracle:
     def __init__(self, kind: str = "f64"):
         self.kind = kind
         self.dtype = _DTYPES[kind]
+        self.Q = _NQ[kind]
         self.lib = load_oracle(kind)
         L = self.lib
         vp = C.c_void_p
@@ -149,14 +155,14 @@ class Oracle:
 
     # ---- tables and per-node operators ---------------------------------
     def lattice(self):
-        c = np.zeros((Q, 3), np.int32)
-        w = np.zeros(Q, np.float64)
+        c = np.zeros((self.Q, 3), np.int32)
+        w = np.zeros(self.Q, np.float64)
         self.lib.or_lattice(_ptr(c), _ptr(w))
         return c, w
 
     def moment_matrix(self, u):
         u = self.arr(u)
-        T = np.zeros((Q, Q), self.dtype)
+        T = np.zeros((self.Q, self.Q), self.dtype)
         self.lib.or_moment_matrix(_ptr(u), _ptr(T))
         return T
 
@@ -171,12 +177,12 @@ class Oracle:
 
     def shift_matrix(self, u):
         u = self.arr(u)
-        N = np.zeros((Q, Q), self.dtype)
+        N = np.zeros((self.Q, self.Q), self.dtype)
         self.lib.or_shift_matrix(_ptr(u), _ptr(N))
         return N
 
     def phi_coeffs(self, ab):
-        out = np.zeros(Q, self.dtype)
+        out = np.zeros(self.Q, self.dtype)
         self.lib.or_phi_coeffs(self._s(ab), _ptr(out))
         return out
 
@@ -188,40 +194,40 @@ class Oracle:
 
     def equilibrium(self, rho, u, ab, nub, grho):
         u, grho = self.arr(u), self.arr(grho)
-        out = np.zeros(Q, self.dtype)
+        out = np.zeros(self.Q, self.dtype)
         self.lib.or_equilibrium(self._s(rho), _ptr(u), self._s(ab), self._s(nub), _ptr(grho), _ptr(out))
         return out
 
     def forcing_pop(self, u, F):
         u, F = self.arr(u), self.arr(F)
-        out = np.zeros(Q, self.dtype)
+        out = np.zeros(self.Q, self.dtype)
         self.lib.or_forcing_pop(_ptr(u), _ptr(F), _ptr(out))
         return out
 
     def collide(self, p: OrParams, f, feq, Fp, u, s2nu):
         f, feq, Fp, u = self.arr(f), self.arr(feq), self.arr(Fp), self.arr(u)
-        out = np.zeros(Q, self.dtype)
+        out = np.zeros(self.Q, self.dtype)
         self.lib.or_collide(C.byref(p), _ptr(f), _ptr(feq), _ptr(Fp), _ptr(u), self._s(s2nu), _ptr(out))
         return out
 
     def perturb(self, p: OrParams, A, gphi):
         g = self.arr(gphi)
-        out = np.zeros(Q, self.dtype)
+        out = np.zeros(self.Q, self.dtype)
         self.lib.or_perturb(C.byref(p), self._s(A), _ptr(g), _ptr(out))
         return out
 
     def recolour(self, p: OrParams, fdag, rho_r, rho_b, ab, gphi):
         fd, g = self.arr(fdag), self.arr(gphi)
-        fr = np.zeros(Q, self.dtype)
-        fb = np.zeros(Q, self.dtype)
+        fr = np.zeros(self.Q, self.dtype)
+        fb = np.zeros(self.Q, self.dtype)
         self.lib.or_recolour(C.byref(p), _ptr(fd), self._s(rho_r), self._s(rho_b), self._s(ab),
                              _ptr(g), _ptr(fr), _ptr(fb))
         return fr, fb
 
     def collide_node(self, p: OrParams, A, fr27, fb27, phi27, rho27):
         a, b, c, d = (self.arr(v) for v in (fr27, fb27, phi27, rho27))
-        Cr = np.zeros(Q, self.dtype)
-        Cb = np.zeros(Q, self.dtype)
+        Cr = np.zeros(self.Q, self.dtype)
+        Cb = np.zeros(self.Q, self.dtype)
         self.lib.or_collide_node(C.byref(p), self._s(A), _ptr(a), _ptr(b), _ptr(c), _ptr(d),
                                  _ptr(Cr), _ptr(Cb))
         return Cr, Cb
@@ -229,9 +235,9 @@ class Oracle:
     # ---- whole lattice ---------------------------------------------------
     def new_state(self, p: OrParams):
         N = p.nx * p.ny * p.nz
-        fr = np.zeros((Q, N), self.dtype)
-        fb = np.zeros((Q, N), self.dtype)
-        hist = np.zeros((2 * Q, p.nx * p.ny), self.dtype)
+        fr = np.zeros((self.Q, N), self.dtype)
+        fb = np.zeros((self.Q, N), self.dtype)
+        hist = np.zeros((2 * self.Q, p.nx * p.ny), self.dtype)
         return fr, fb, hist
 
     def init_fields(self, p: OrParams, rho_r, rho_b, u=None):
