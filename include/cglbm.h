@@ -17,7 +17,9 @@
  *
  * Conventions shared by every entry point:
  *   - Lattice: nx*ny*nz nodes, node index n = (z*ny + y)*nx + x (x fastest).
- *     Directions i = 0..26 follow the paper's velocity set (Eq. velVec).
+ *     Directions i = 0..26 follow the paper's velocity set (Eq. velVec);
+ *     with lattice == 19 (D3Q19, see lbm_params) i = 0..18, the same order
+ *     without the eight corners.
  *   - Memory: the caller owns all device memory.  lbm_query_sizes() states
  *     the size of every buffer; the library stores the raw device pointers
  *     handed to lbm_init() and never allocates or frees device memory.
@@ -90,21 +92,41 @@ typedef struct lbm_params {
     uint64_t noise_seed;  /* seed of the counter-based SplitMix64 noise */
     /* droplet preset (init == LBM_INIT_DROPLET): centre, radius, interface width W */
     double drop_cx, drop_cy, drop_cz, drop_R, drop_W;
+    /* velocity set: 27 (or 0) the paper's D3Q27; 19 the reduced D3Q19 lattice
+       that Sec. II and Sec. IV B suggest to cut the cost, with coefficients
+       derived by keeping every moment the D3Q27 ones fix: weights 1/3, 1/18,
+       1/36; varphi_i = alpha at rest and 1.5 w_i (1 - alpha) otherwise (so
+       alpha_b = 1/3 gives c_s^2 = 1/3); Phi_i = -3 nu_bar u.grad rho at rest and
+       m_i nu_bar (c.u)(c.grad rho)/4 with m = 2 (faces), 1 (edges); B_i = -1/3
+       at rest and w_i otherwise; the 19 rows of Eq. momentSet that are
+       independent on D3Q19.  D3Q19 supports bc == LBM_BC_PERIODIC, storage
+       FP32 and the fields and droplet presets (else LBM_ERR_UNSUPPORTED), at
+       most 2^31 nodes, and the entry points lbm_query_sizes, lbm_init,
+       lbm_step, lbm_macroscopic, lbm_get_state, lbm_set_state, lbm_time,
+       lbm_profile, lbm_profile_read and lbm_destroy; the snapshot, adjoint
+       and jet-diagnostics calls return LBM_ERR_UNSUPPORTED.  Q below is 27,
+       or 19 for D3Q19. */
+    int32_t lattice;
+    int32_t lattice_pad;  /* unused */
 } lbm_params;
 
 /* Byte sizes of the caller-allocated device buffers. */
 typedef struct lbm_sizes {
     uint64_t n_nodes;
     uint64_t pop_bytes;     /* each of the two population buffers (A and B): 54 planes of
-                               (nx+2)(ny+2)(nz+2) padded nodes in the storage format */
+                               (nx+2)(ny+2)(nz+2) padded nodes in the storage format
+                               (D3Q19: the larger of 39 planes of N floats, the form
+                               init and set_state write, and the 19 planes plus a 16-byte
+                               record per node that a step writes) */
     uint64_t field_bytes;   /* per-node fields and recolouring scalars: 11 floats per padded node
-                               (19 with the reference records of BF16_EQ / FP16_EQ) */
+                               (19 with the reference records of BF16_EQ / FP16_EQ; D3Q19:
+                               4 floats per node) */
     uint64_t hist_bytes;    /* outlet planes of the previous and current step, 2 x 54 floats
                                per (x, y); jet only */
     uint64_t audit_bytes;   /* FP64 partial sums of the audit reduction */
     uint64_t inlet_bytes;   /* optional inlet axial-velocity profile, nx*ny floats */
     uint64_t adjoint_bytes; /* adjoint work buffer (see lbm_adjoint_step) */
-    uint64_t state_bytes;   /* a full FP32 state: 54 floats per node (fr[27], fb[27]) */
+    uint64_t state_bytes;   /* a full FP32 state: 2Q floats per node (fr[Q], fb[Q]) */
     uint64_t snap_bytes;    /* one state snapshot in the library's own layout (see lbm_step_into):
                                27 population planes of (nx+2)(ny+2)(nz+2) padded nodes in the
                                storage format (28 for BF16_EQ / FP16_EQ), a 16-byte record per
@@ -156,7 +178,8 @@ int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* 
                     double* audit);
 
 /* Copy the current state (time lbm_time()) into a device array of
- * state_bytes: fr[i*N + n] for i < 27, then fb[i*N + n]. */
+ * state_bytes: fr[i*N + n] for i < Q, then fb[i*N + n] (the populations
+ * after streaming, Q = 27 or 19 by p->lattice). */
 int lbm_get_state(lbm_handle* h, float* state);
 
 /* Replace the current state by a device array in the lbm_get_state layout

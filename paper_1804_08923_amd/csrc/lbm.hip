@@ -12,6 +12,7 @@
 #include "lbm_adjoint.h"
 #include "lbm_diag.h"
 #include "lbm_kernels.h"
+#include "lbm_q19.h"
 
 using namespace cglbm;
 
@@ -37,12 +38,14 @@ struct StateSet {
 
 struct lbm_handle {
     lbm_params p;
+    int q19;            // D3Q19 lattice (lbm_q19.h): own buffers only, no snapshots or adjoint
     KP k;
     StateSet own[2];    // the handle's A and B sets (caller buffers given to lbm_init)
     StateSet ext;       // a caller snapshot that lbm_step_into made current
     int cs;             // current set: 0 or 1 (own), 2 (ext)
     float2* PD;         // (phi, rho - rho_b0) per padded node
     float* XR;          // tagged minority-colour fraction per padded node
+    float4* PD4;        // D3Q19: (phi, rho - rho_b0, rho_r, rho_b) per node
     double* audit;
     void* adjoint;
     hipStream_t stream;
@@ -104,9 +107,20 @@ uint64_t padded_nodes(const lbm_params* p)
     return (uint64_t)(p->nx + 2) * (uint64_t)(p->ny + 2) * (uint64_t)(p->nz + 2);
 }
 
+bool is_q19(const lbm_params* p) { return p->lattice == 19; }
+
 int validate(const lbm_params* p)
 {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
+    if (p->lattice != 0 && p->lattice != 27 && p->lattice != 19)
+        return fail(LBM_ERR_INVALID_ARG, "unknown lattice %d (19 or 27)", p->lattice);
+    if (is_q19(p)) {
+        if (p->bc != LBM_BC_PERIODIC || p->storage != LBM_STORAGE_FP32)
+            return fail(LBM_ERR_UNSUPPORTED, "the D3Q19 lattice is implemented for periodic lattices in FP32 only");
+        if (p->init == LBM_INIT_JET) return fail(LBM_ERR_UNSUPPORTED, "the jet preset needs the D3Q27 lattice");
+        if ((uint64_t)p->nx * p->ny * p->nz > (1ull << 31))
+            return fail(LBM_ERR_UNSUPPORTED, "the D3Q19 lattice holds at most 2^31 nodes");
+    }
     if (p->bc != LBM_BC_PERIODIC && p->bc != LBM_BC_JET) return fail(LBM_ERR_INVALID_ARG, "unknown bc %d", p->bc);
     if (p->storage < LBM_STORAGE_FP32 || p->storage > LBM_STORAGE_FP16_EQ)
         return fail(LBM_ERR_INVALID_ARG, "unknown storage %d", p->storage);
@@ -175,7 +189,7 @@ void fill_kp(const lbm_params* p, const float* inlet, KP* k)
     k->alpha_r = (float)ar;
     k->alpha_b = (float)p->alpha_b;
     k->dalpha = (float)(ar - p->alpha_b);
-    k->a_minus_w0 = (float)(p->alpha_b - 8.0 / 27.0);
+    k->a_minus_w0 = (float)(p->alpha_b - (is_q19(p) ? 1.0 / 3.0 : 8.0 / 27.0));
     k->kappa_b_m1 = (float)(27.0 * (1.0 - p->alpha_b) / 19.0 - 1.0);
     k->inv_nu_r = (float)(1.0 / p->nu_r);
     k->inv_nu_b = (float)(1.0 / p->nu_b);
@@ -319,6 +333,17 @@ int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
     const uint64_t plane = (uint64_t)p->nx * p->ny;
     const uint64_t nblk = ((plane + BLOCK - 1) / BLOCK) * (uint64_t)p->nz;
     out->n_nodes = N;
+    if (is_q19(p)) {
+        out->pop_bytes = q19::pop_bytes(N);
+        out->field_bytes = 16ull * N;
+        out->hist_bytes = 0;
+        out->audit_bytes = (nblk + 1) * 5 * sizeof(double);
+        out->inlet_bytes = plane * sizeof(float);
+        out->adjoint_bytes = 0;
+        out->state_bytes = 2ull * q19::Q19 * N * sizeof(float);
+        out->snap_bytes = 0;
+        return LBM_OK;
+    }
     out->pop_bytes = 2ull * Q * NP * elem_bytes(p->storage);
     out->field_bytes = field_floats(p->storage) * NP * sizeof(float);
     out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * 2ull * Q * plane * sizeof(float) : 0;
@@ -354,6 +379,7 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     lbm_handle* H = new (std::nothrow) lbm_handle();
     if (!H) return fail(LBM_ERR_INVALID_ARG, "out of host memory");
     H->p = *p;
+    H->q19 = is_q19(p);
     fill_kp(p, buf->inlet_uz, &H->k);
     const size_t NP = H->k.NP;
     H->own[0].pop = buf->pop_a;
@@ -385,6 +411,24 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->ncells = (uint32_t)cells;
     H->grid_shell = dim3((unsigned)((cells + BLOCK - 1) / BLOCK));
     H->nblk = (int)(H->grid_all.x * H->grid_all.y);
+    if (H->q19) {
+        H->PD4 = (float4*)buf->fields;
+        H->PD = nullptr;
+        H->XR = nullptr;
+        H->own[0].R = H->own[1].R = nullptr;
+        H->own[0].Q = H->own[1].Q = nullptr;
+        const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
+        hipLaunchKernelGGL(q19::k19_init, H->grid_all, dim3(BLOCK), 0, H->stream, (float*)H->own[0].pop, H->k,
+                           p->init, rho_r, rho_b, u, p->drop_cx, p->drop_cy, p->drop_cz, p->drop_R, p->drop_W,
+                           p->rho_r0, p->rho_b0, ar, p->alpha_b);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            delete H;
+            return fail(LBM_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+        }
+        *h = H;
+        return LBM_OK;
+    }
     rc = dispatch(p->bc, p->storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         (void)bc;
@@ -409,8 +453,49 @@ namespace {
 
 // One full time step from the current state into the state set dst, which
 // becomes the current state.
+int q19_step(lbm_handle* h, const StateSet& dst_set, int dst_cs)
+{
+    const KP k = read_kp(h);
+    const float* src = (const float*)cur_set(h).pop;
+    float* dst = (float*)dst_set.pop;
+    hipEvent_t* e = nullptr;
+    if (h->profiling) {
+        while (h->ev.size() < h->ev_used + 5) {
+            hipEvent_t x;
+            HIP_CHECK(hipEventCreate(&x));
+            h->ev.push_back(x);
+        }
+        e = &h->ev[h->ev_used];
+        h->ev_used += 5;
+        HIP_CHECK(hipEventRecord(e[0], h->stream));
+    }
+    if (h->unshifted)
+        hipLaunchKernelGGL(q19::k19_density<true>, h->grid_all, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
+    else
+        hipLaunchKernelGGL(q19::k19_density<false>, h->grid_all, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
+    LAUNCH_CHECK();
+    if (e) {
+        HIP_CHECK(hipEventRecord(e[1], h->stream));
+        HIP_CHECK(hipEventRecord(e[2], h->stream));
+    }
+    if (h->unshifted)
+        hipLaunchKernelGGL(q19::k19_collide<true>, h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4, k);
+    else
+        hipLaunchKernelGGL(q19::k19_collide<false>, h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4, k);
+    LAUNCH_CHECK();
+    if (e) {
+        HIP_CHECK(hipEventRecord(e[3], h->stream));
+        HIP_CHECK(hipEventRecord(e[4], h->stream));
+    }
+    h->cs = dst_cs;
+    h->t += 1;
+    h->unshifted = 0;
+    return LBM_OK;
+}
+
 int step_once(lbm_handle* h, const StateSet& dst_set, int dst_cs)
 {
+    if (h->q19) return q19_step(h, dst_set, dst_cs);
     return dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         using T = typename S::T;
@@ -513,6 +598,7 @@ int lbm_step(lbm_handle* h, int32_t n_steps)
 int lbm_step_into(lbm_handle* h, void* snap)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (h->q19) return fail(LBM_ERR_UNSUPPORTED, "snapshots need the D3Q27 lattice");
     StateSet s;
     int rc = snap_set(h, snap, &s);
     if (rc != LBM_OK) return rc;
@@ -524,6 +610,7 @@ int lbm_step_into(lbm_handle* h, void* snap)
 int lbm_snapshot_save(lbm_handle* h, void* snap)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (h->q19) return fail(LBM_ERR_UNSUPPORTED, "snapshots need the D3Q27 lattice");
     if (h->unshifted) return fail(LBM_ERR_STATE, "the current state is a general state (after init or set_state)");
     StateSet s;
     int rc = snap_set(h, snap, &s);
@@ -534,6 +621,7 @@ int lbm_snapshot_save(lbm_handle* h, void* snap)
 int lbm_snapshot_load(lbm_handle* h, const void* snap, int64_t t)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (h->q19) return fail(LBM_ERR_UNSUPPORTED, "snapshots need the D3Q27 lattice");
     if (t < 0) return fail(LBM_ERR_INVALID_ARG, "t < 0");
     StateSet s;
     int rc = snap_set(h, snap, &s);
@@ -551,7 +639,18 @@ int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* 
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
     const KP k = read_kp(h);
-    int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
+    int rc = h->q19 ? [&]() -> int {
+        const float* pop = (const float*)cur_set(h).pop;
+        double* part = audit ? h->audit : nullptr;
+        if (h->unshifted)
+            hipLaunchKernelGGL(q19::k19_macro<true>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, rho_r, rho_b,
+                               u, phi, part);
+        else
+            hipLaunchKernelGGL(q19::k19_macro<false>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, rho_r, rho_b,
+                               u, phi, part);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    }() : dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         constexpr int BC = decltype(bc)::value;
         hipLaunchKernelGGL((k_macro<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
@@ -576,6 +675,15 @@ int lbm_get_state(lbm_handle* h, float* state)
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
     if (!state) return fail(LBM_ERR_INVALID_ARG, "state is NULL");
     const KP k = read_kp(h);
+    if (h->q19) {
+        const float* pop = (const float*)cur_set(h).pop;
+        if (h->unshifted)
+            hipLaunchKernelGGL(q19::k19_get_state<true>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, state);
+        else
+            hipLaunchKernelGGL(q19::k19_get_state<false>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, state);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    }
     return dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         constexpr int BC = decltype(bc)::value;
@@ -594,6 +702,15 @@ int lbm_set_state(lbm_handle* h, const float* state, int64_t t)
     // the general state goes into an own set (a current snapshot is not overwritten)
     const int d = h->cs == 2 ? 0 : h->cs;
     const KP k = read_kp(h);
+    if (h->q19) {
+        hipLaunchKernelGGL(q19::k19_set_state, h->grid_all, dim3(BLOCK), 0, h->stream, (float*)h->own[d].pop, k,
+                           state);
+        LAUNCH_CHECK();
+        h->cs = d;
+        h->t = t;
+        h->unshifted = 1;
+        return LBM_OK;
+    }
     int rc = dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
         using S = decltype(st);
         (void)bc;
@@ -654,6 +771,7 @@ int adjoint_args(lbm_handle* h, const void* state_t, int64_t t, const float* lam
                  double* dJ_dA)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (h->q19) return fail(LBM_ERR_UNSUPPORTED, "the adjoint step needs the D3Q27 lattice");
     if (!h->adjoint) return fail(LBM_ERR_STATE, "no adjoint work buffer was given to lbm_init");
     if (!state_t || !lambda_in || !lambda_out || !dJ_dA)
         return fail(LBM_ERR_INVALID_ARG, "state_t, lambda_in, lambda_out and dJ_dA are required");
@@ -830,6 +948,7 @@ int diag_run(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, 
 int diag_args(lbm_handle* h, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
+    if (h->q19) return fail(LBM_ERR_UNSUPPORTED, "the jet diagnostics need the D3Q27 lattice");
     if (!stats) return fail(LBM_ERR_INVALID_ARG, "stats is required");
     if (cap < 0 || (cap > 0 && !volumes)) return fail(LBM_ERR_INVALID_ARG, "volumes is NULL with cap > 0");
     return LBM_OK;

@@ -41,6 +41,7 @@ class lbm_params(C.Structure):
         ("noise_amp", C.c_double), ("noise_seed", C.c_uint64),
         ("drop_cx", C.c_double), ("drop_cy", C.c_double), ("drop_cz", C.c_double),
         ("drop_R", C.c_double), ("drop_W", C.c_double),
+        ("lattice", C.c_int32), ("lattice_pad", C.c_int32),
     ]
 
 
@@ -125,6 +126,7 @@ def make_params(prob: Problem) -> lbm_params:
     p.noise_amp, p.noise_seed = prob.noise_amp, prob.noise_seed
     c = prob.center
     p.drop_cx, p.drop_cy, p.drop_cz, p.drop_R, p.drop_W = c[0], c[1], c[2], prob.drop_R, prob.drop_W
+    p.lattice = prob.lattice
     return p
 
 
@@ -150,6 +152,7 @@ class LBM:
         self.torch = torch
         self.lib = load_library()
         self.prob = prob
+        self.Q = prob.lattice      # directions per colour: 27, or 19 on D3Q19
         self.device = torch.device(device)
         self.params = make_params(prob)
         self.sizes = lbm_query_sizes(self.params)
@@ -204,13 +207,13 @@ class LBM:
         return out
 
     def get_state(self):
-        st = self.torch.empty((2 * Q, self.sizes.n_nodes), dtype=self.torch.float32, device=self.device)
+        st = self.torch.empty((2 * self.Q, self.sizes.n_nodes), dtype=self.torch.float32, device=self.device)
         _check(self.lib, self.lib.lbm_get_state(self.h, st.data_ptr()))
         return st
 
     def set_state(self, state, t: int = 0):
         st = self.torch.as_tensor(state, dtype=self.torch.float32, device=self.device).contiguous()
-        assert st.numel() == 2 * Q * self.sizes.n_nodes
+        assert st.numel() == 2 * self.Q * self.sizes.n_nodes
         self._set_state_keep = st
         _check(self.lib, self.lib.lbm_set_state(self.h, st.data_ptr(), int(t)))
 
@@ -243,7 +246,7 @@ class LBM:
         """One reverse step (see lbm_adjoint_step): lam_out = (d x_{t+1}/d x_t)^T lam_in;
         dJ_dA (float64, 1 element) and dJ_du_in (float32, nx*ny) are incremented."""
         for a in (state_t, lam_in, lam_out):
-            assert a.dtype == self.torch.float32 and a.is_contiguous() and a.numel() == 2 * Q * self.sizes.n_nodes
+            assert a.dtype == self.torch.float32 and a.is_contiguous() and a.numel() == 2 * self.Q * self.sizes.n_nodes
         assert dJ_dA.dtype == self.torch.float64 and dJ_dA.numel() >= 1
         if dJ_du_in is not None:
             assert dJ_du_in.dtype == self.torch.float32 and dJ_du_in.numel() == self.prob.nx * self.prob.ny
@@ -253,7 +256,7 @@ class LBM:
     def adjoint_step_snapshot(self, snap_t, t: int, lam_in, lam_out, dJ_dA, dJ_du_in=None):
         """adjoint_step with the forward state at time t given as a snapshot."""
         for a in (lam_in, lam_out):
-            assert a.dtype == self.torch.float32 and a.is_contiguous() and a.numel() == 2 * Q * self.sizes.n_nodes
+            assert a.dtype == self.torch.float32 and a.is_contiguous() and a.numel() == 2 * self.Q * self.sizes.n_nodes
         assert dJ_dA.dtype == self.torch.float64 and dJ_dA.numel() >= 1
         if dJ_du_in is not None:
             assert dJ_du_in.dtype == self.torch.float32 and dJ_du_in.numel() == self.prob.nx * self.prob.ny

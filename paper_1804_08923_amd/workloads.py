@@ -48,6 +48,7 @@ class Problem:
     drop_center: Optional[Tuple[float, float, float]] = None
     steps: int = 200
     storage: str = "fp32"         # "fp32" | "bf16" | "fp16" | "bf16eq" | "fp16eq"
+    lattice: int = 27             # 27 (D3Q27) | 19 (D3Q19; its colours take alpha_b = 1/3)
     meta: dict = field(default_factory=dict)
 
     @property

@@ -56,10 +56,10 @@ def sphere_blobs(nx, ny, nz, seed, n_blobs, r_min=0.8, r_max=4.0):
     return np.where(inside, mag, -mag).ravel()
 
 
-def population_noise(n_nodes, seed, amp=1e-4):
-    """Independent noise for the 2 x 27 populations of every node."""
+def population_noise(n_nodes, seed, amp=1e-4, q=27):
+    """Independent noise for the 2 x q populations of every node."""
     rng = np.random.default_rng(seed + 13)
-    return amp * rng.standard_normal((2, 27, n_nodes))
+    return amp * rng.standard_normal((2, q, n_nodes))
 
 
 def population_noise_planes(n_nodes, seed, amp=1e-4):

@@ -106,3 +106,28 @@ def test_null_handle_is_rejected(lib):
     assert lib.lbm_step(None, 1) == -5
     assert lib.lbm_destroy(None) == 0
     assert lib.lbm_time(None) == -1
+
+
+def test_q19_sizes_and_validation(lib):
+    """lattice = 19 (D3Q19): buffer sizes of its two state forms, and the
+    configurations it does not implement (16-bit storage, the jet) are
+    LBM_ERR_UNSUPPORTED; a lattice other than 19 or 27 is invalid."""
+    prob = droplet_small().replace(lattice=19, alpha_b=1 / 3, nx=13, ny=7, nz=5)
+    s = lbm.lbm_query_sizes(lbm.make_params(prob))
+    N = 13 * 7 * 5
+    a = lambda b: (b + 255) // 256 * 256
+    assert s.n_nodes == N
+    assert s.pop_bytes == max(39 * N * 4, a(76 * N) + 16 * N)
+    assert s.state_bytes == 38 * N * 4 and s.field_bytes == 16 * N
+    assert s.snap_bytes == 0 and s.adjoint_bytes == 0 and s.hist_bytes == 0
+    big = prob.replace(nx=256, ny=256, nz=1024)
+    assert lbm.lbm_query_sizes(lbm.make_params(big)).pop_bytes == 39 * 256 * 256 * 1024 * 4
+    r = lbm.lbm_sizes()
+    for bad, code in ((prob.replace(storage="bf16"), -2), (jet_128().replace(lattice=19, alpha_b=1 / 3), -2),
+                      (prob.replace(init="jet"), -2), (prob.replace(lattice=23), -1)):
+        assert lib.lbm_query_sizes(C.byref(lbm.make_params(bad)), C.byref(r)) == code
+        assert lib.lbm_last_error().decode() != ""
+    # 0 (a zeroed parameter block) still means D3Q27
+    p = lbm.make_params(droplet_small())
+    p.lattice = 0
+    assert lib.lbm_query_sizes(C.byref(p), C.byref(r)) == 0 and r.pop_bytes == 54 * 34 ** 3 * 4
