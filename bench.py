@@ -17,6 +17,9 @@ roofline = the fused kernel's algorithmic bytes per launch / its average
 duration in the profiled pass, against the 8 TB/s HBM peak.
 cpu_baseline = the FP64 oracle on the host cores, on a bounded slab sample of
 the same jet, on all threads and on one.
+lattices = the reduced D3Q19 lattice (Sec. II's suggested cost cut) against
+D3Q27 on a periodic droplet box of the same size (the jet boundaries exist
+for D3Q27 only), each with its own kernel timings and roofline.
 """
 from __future__ import annotations
 
@@ -47,24 +50,32 @@ DENSITY_BYTES = {"fp32": 27 * 4 + 16 + 12, "bf16": 27 * 2 + 16 + 12, "fp16": 27 
 PAPER_CONTEXT = {"mlups": [1.2, 12.0], "hardware": "unspecified cluster (COMA / Earth Simulator named)",
                  "workload": "240x240x1200 UT jet, 20000 iterations in ~32 h"}
 PROFILE_STEPS = 50
+# D3Q19 (lattice = 19), bytes per node update.  Collision kernel: 19 pulled
+# deviations read, the float4 (phi, rho - rho_b0, rho_r, rho_b) read, 19
+# deviations and the float4 recolouring record written.  Density pass: 19
+# deviations and the source-node record read, the float4 written.  Reference
+# model: both colour sets (2 x 19 populations) read once and written once.
+Q19_FUSED_BYTES = 19 * 4 + 16 + 19 * 4 + 16
+Q19_DENSITY_BYTES = 19 * 4 + 16 + 16
+Q19_STEP_BYTES = 2 * 2 * 19 * 4
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(storage, workload):
+def measured_traffic(storage, workload, kernel="k_collide"):
     """HBM bytes per fused-kernel launch from committed rocprofv3 counter runs,
     used only while the kernel source is unchanged since they were taken and
     only for the workload they were taken on."""
-    from paper_1804_08923_amd.profiling import kernel_source_hash
+    from paper_1804_08923_amd.profiling import kernel_source_hash, sources_of
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     ent = t.get(f"{workload}/{storage}")
-    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+    if not ent or ent.get("kernel_hash") != kernel_source_hash(sources_of(kernel)):
         return None
     return ent.get("bytes_per_launch")
 
@@ -187,6 +198,44 @@ def adjoint_leg(prob, fwd_ms, nadj=10):
                 gradient_step_ms=fwd_ms + rec_ms + adj_ms)
 
 
+def lattice_legs(jet, steps, warmup):
+    """D3Q19 against D3Q27 at equal lattice size and boundaries: a periodic box
+    of the jet's size holding one droplet (R = nx/4, W = 4) at the jet's
+    density ratio, with the Table I viscosity (tau = 1) and A = 1e-3 (a static
+    droplet at the jet's tau ~ 0.5 is not a stable test case; the work per node
+    does not depend on them); alpha_b gives the blue phase c_s^2 = 1/3 on each
+    lattice.  Returns per-lattice MLUPS and kernel timings."""
+    from paper_1804_08923_amd.workloads import Problem
+    base = Problem(name=f"droplet-{jet.nx}x{jet.ny}x{jet.nz}", nx=jet.nx, ny=jet.ny, nz=jet.nz, bc="periodic",
+                   rho_r0=jet.rho_r0, rho_b0=jet.rho_b0, nu_r=1.0 / 6.0, nu_b=1.0 / 6.0, A=1e-3, beta=jet.beta,
+                   drop_R=jet.nx / 4.0, drop_W=4.0, init="droplet", storage="fp32")
+    out = {}
+    for q in (27, 19):
+        prob = base.replace(lattice=q, alpha_b=1.0 / 3.0 if q == 19 else 8.0 / 27.0)
+        r = run_leg(prob, steps, warmup)
+        fb = Q19_FUSED_BYTES if q == 19 else FUSED_BYTES["fp32"]
+        db = Q19_DENSITY_BYTES if q == 19 else DENSITY_BYTES["fp32"]
+        sb = Q19_STEP_BYTES if q == 19 else STEP_BYTES["fp32"]
+        N = prob.n_nodes
+        out[f"d3q{q}"] = {
+            "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+            "fused_kernel_ms": round(r["fused_ms"], 4), "density_kernel_ms": round(r["density_ms"], 4),
+            "fused_bytes_per_node": fb, "density_bytes_per_node": db,
+            "fused_kernel_gbs": round(fb * N / (r["fused_ms"] * 1e-3) / 1e9, 1),
+            "density_kernel_gbs": round(db * N / (r["density_ms"] * 1e-3) / 1e9, 1),
+            "step_bytes_per_node": sb,
+            "step_roofline_frac": round(r["mlups"] / (HBM_PEAK_GBS * 1e9 / sb / 1e6), 4),
+            "impl_roofline_frac": round(r["mlups"] / (HBM_PEAK_GBS * 1e9 / (fb + db) / 1e6), 4),
+            "finite": r["finite"]}
+        if q == 19:
+            out["d3q19"]["fused_traffic"] = measured_traffic("d3q19", base.name, kernel="k19_collide")
+        log(f"bench: {prob.name} D3Q{q}: {r['mlups']:.0f} MLUPS, fused {r['fused_ms']:.3f} ms, density "
+            f"{r['density_ms']:.3f} ms")
+    out["workload"] = base.name
+    out["d3q19_x_d3q27"] = round(out["d3q19"]["mlups"] / out["d3q27"]["mlups"], 3)
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -241,6 +290,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true", help="skip the BF16/FP16 storage legs")
     ap.add_argument("--legs", default="bf16,fp16,bf16eq,fp16eq", help="storage legs to run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-step timing")
+    ap.add_argument("--no-lattices", action="store_true", help="skip the D3Q19 / D3Q27 periodic comparison")
+    ap.add_argument("--lattice-steps", type=int, default=1000, help="timed steps of each lattice leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (calibrates hardware byte counters)")
     args = ap.parse_args()
@@ -297,6 +348,10 @@ def main():
                        "adjoint step; the checkpoint load is paid once per segment"}
         log(f"bench: adjoint step {a['adjoint_ms']:.3f} ms = {adj['ratio']:.2f}x forward, recompute "
             f"{a['recompute_ms']:.3f} ms = {adj['recompute_ratio']:.2f}x, gradient step {adj['gradient_step_ratio']:.2f}x")
+    lat = None
+    if not args.no_lattices:
+        lat = lattice_legs(prob, args.lattice_steps, 200)
+        log(f"bench: D3Q19 / D3Q27 on {lat['workload']}: {lat['d3q19_x_d3q27']:.2f}x")
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
@@ -337,6 +392,7 @@ def main():
         "storage_legs": legs,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,
+        "lattices": lat,
         "finite": main_leg["finite"],
         "paper_context": PAPER_CONTEXT,
     }

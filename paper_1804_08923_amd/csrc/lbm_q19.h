@@ -76,7 +76,13 @@ __host__ inline uint64_t pop_bytes(uint64_t N)
     return general > shifted ? general : shifted;
 }
 
-// This thread's node and the wrapped neighbour coordinates.
+// This thread's node and the wrapped neighbour coordinates.  Blocks are handed
+// to the 8 XCDs round-robin (block b of a plane goes to XCD b mod 8 when a
+// plane has a multiple of 8 blocks); the plane's blocks are permuted so that
+// each XCD takes a contiguous band of them, whose y- and z-neighbour rows are
+// then fetched into that XCD's L2 only, instead of into three.
+constexpr uint32_t kXcds = 8;
+
 struct Site {
     uint32_t n;                    // node index
     uint32_t xs[3], ys[3], zs[3];  // x - 1, x, x + 1; (y - 1, y, y + 1) nx; (z - 1, z, z + 1) nx ny
@@ -86,7 +92,9 @@ struct Site {
 __device__ __forceinline__ Site site(const KP& k)
 {
     Site s;
-    const uint32_t p = blockIdx.x * (uint32_t)BLOCK + threadIdx.x;
+    const uint32_t B = gridDim.x, b = blockIdx.x;
+    const uint32_t pb = (B % kXcds == 0) ? (b % kXcds) * (B / kXcds) + b / kXcds : b;
+    const uint32_t p = pb * (uint32_t)BLOCK + threadIdx.x;
     s.valid = p < k.plane;
     const int z = (int)blockIdx.y;
     const int y = (int)(((uint64_t)p * k.nx_mul) >> k.nx_sh);
@@ -229,8 +237,7 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
     const double kap = 1.5 * (1.0 - ab) * m - 1.5 * amw * k.rho_b0;  // 1.5 (1 - ab) rho - rho_b0
     // e_i = feq_i - w_i rho_b0 (Eq. EES, Eq. Phi) plus half the forcing
     // population (Eq. ketFd): the post-collision value without the
-    // non-equilibrium part; evaluated twice (for Pi^g, then for the store)
-    // instead of keeping 19 doubles live
+    // non-equilibrium part
     auto eq_half_force = [&](int i) -> double {
         const double cu = kCX[i] * ux + kCY[i] * uy + kCZ[i] * uz;
         const double cF = kCX[i] * Fx + kCY[i] * Fy + kCZ[i] * Fz;
@@ -245,14 +252,17 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
         }
         return e + 0.5 * w19(i) * (3.0 * (cF - uF) + 9.0 * cu * cF);
     };
-    // Pi^g of g = f - feq + F'/2 = d - (e + F'/2) + F'
+    // Pi^g of g = f - feq + F'/2 from closed forms of the moments of feq and F'
+    // (both lattices' coefficients give them): sum feq c c = rho [(1 - ab)/2 I
+    // + u u] + nu_bar [u grad rho + grad rho u + (u . grad rho) I] (Eqs. EES,
+    // Phi), sum F' c c = u F + F u (Eq. ketFd), sum w_i rho_b0 c c = rho_b0/3 I.
+    // Only the deviatoric part is used, so the isotropic terms are left out:
+    // dev Pi^g = dev [sum d c c - rho u u - nu_bar (u grad rho + grad rho u)
+    //                 + (u F + F u)/2]
     double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
     for (int i = 1; i < Q19; ++i) {
-        const double cF = kCX[i] * Fx + kCY[i] * Fy + kCZ[i] * Fz;
-        const double cu = kCX[i] * ux + kCY[i] * uy + kCZ[i] * uz;
-        const double hF = 0.5 * w19(i) * (3.0 * (cF - uF) + 9.0 * cu * cF);
-        const double g = (double)d[i] - eq_half_force(i) + 2.0 * hF;
+        const double g = (double)d[i];
         if (kCX[i]) pxx += g;
         if (kCY[i]) pyy += g;
         if (kCZ[i]) pzz += g;
@@ -260,6 +270,12 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
         if (kCX[i] && kCZ[i]) pxz += kCX[i] * kCZ[i] * g;
         if (kCY[i] && kCZ[i]) pyz += kCY[i] * kCZ[i] * g;
     }
+    pxx += -rho * ux * ux - 2.0 * nub * ux * grx + ux * Fx;
+    pyy += -rho * uy * uy - 2.0 * nub * uy * gry + uy * Fy;
+    pzz += -rho * uz * uz - 2.0 * nub * uz * grz + uz * Fz;
+    pxy += -rho * ux * uy - nub * (ux * gry + uy * grx) + 0.5 * (ux * Fy + uy * Fx);
+    pxz += -rho * ux * uz - nub * (ux * grz + uz * grx) + 0.5 * (ux * Fz + uz * Fx);
+    pyz += -rho * uy * uz - nub * (uy * grz + uz * gry) + 0.5 * (uy * Fz + uz * Fy);
     // (1 - s2nu) times the deviatoric central second moments
     const double om = 1.0 - s2, tr3 = (pxx + pyy + pzz) * (1.0 / 3.0);
     const double k200 = om * (pxx - tr3), k020 = om * (pyy - tr3), k002 = om * (pzz - tr3);

@@ -24,14 +24,20 @@ import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 KERNEL_SOURCES = ("lbm_kernels.h", "lbm_lattice.h")
+Q19_SOURCES = ("lbm_q19.h", "lbm_lattice.h")  # the D3Q19 kernels (k19_*)
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
 
 
-def kernel_source_hash() -> str:
+def sources_of(kernel: str):
+    """The source files a kernel is built from (D3Q19 kernels are k19_*)."""
+    return Q19_SOURCES if "k19_" in kernel else KERNEL_SOURCES
+
+
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     """Hash of the kernel sources; counter figures are valid only for it."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -105,7 +111,7 @@ def main(argv):
         _, _, fdb, wdb, key, kernel, out = argv
         t = traffic(fdb, wdb, kernel)
         t["kernel"] = kernel
-        t["kernel_hash"] = kernel_source_hash()
+        t["kernel_hash"] = kernel_source_hash(sources_of(kernel))
         allt = {}
         if os.path.exists(out):
             with open(out) as fh:
