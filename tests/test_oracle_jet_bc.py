@@ -33,14 +33,20 @@ code:
   of that streamed plane at the new time level.
 * symmetry: a noise-free jet on a square cross-section keeps the symmetries of
   the square (x -> nx-1-x, y -> ny-1-y, x <-> y), which fixes the inlet centre.
+
+Every pin runs on the D3Q27 oracle and on its D3Q19 build (the boundary code
+is the same; the closed forms take each lattice's sums).
 """
 import numpy as np
 import pytest
 
-from oracle import make_params
+from oracle import Oracle, make_params
 from paper_1804_08923_amd.workloads import Problem
 
-Q = 27
+
+@pytest.fixture(scope="module", params=["f64", "q19"])
+def orc(request):
+    return Oracle(request.param)
 
 
 @pytest.fixture(scope="module")
@@ -51,6 +57,7 @@ def lat(orc):
 
 def _mirror_table(c):
     """mirror[i, m]: direction i with the components in mask m (bit 0 x, 1 y, 2 z) reversed."""
+    Q = len(c)
     idx = {tuple(v): i for i, v in enumerate(c)}
     out = np.zeros((Q, 8), np.int64)
     for i in range(Q):
@@ -73,9 +80,10 @@ def _grid(p):
     return x.ravel(), y.ravel(), z.ravel()
 
 
-def _kappa(alpha):
-    """varphi_i(alpha) = w_i kappa(alpha) for |c_i| >= 1 (Eq. varphi_ik)."""
-    return 27.0 * (1.0 - alpha) / 19.0
+def _kappa(alpha, w0):
+    """varphi_i(alpha) = w_i kappa(alpha) for |c_i| >= 1 (Eq. varphi_ik):
+    kappa = (1 - alpha)/(1 - w_0), 27 (1 - alpha)/19 on D3Q27."""
+    return (1.0 - alpha) / (1.0 - w0)
 
 
 # ---------------------------------------------------------------- free slip
@@ -104,6 +112,7 @@ def test_free_slip_equals_mirror_image(orc, lat, dims, seed):
     lattice of 2nx x 2ny x 2nz holding the mirrored state, up to the planes
     the convective outlet has reached (two planes per step)."""
     c, _ = lat
+    Q = len(c)
     mir = _mirror_table(c)
     nx, ny, nz = dims
     prob = _jet(nx, ny, nz)
@@ -178,6 +187,7 @@ def test_first_step_blue_loss_through_inlet_face(orc, lat):
     phi = +1 and every other ghost cell mirrors phi = -1:
         grad phi = 3 sum_i w_i phi(x + c_i) c_i = 6 sum_{i: c_z = -1, x + c_i in inlet} w_i c_i."""
     c, w = lat
+    Q = len(c)
     prob = _jet(12, 11, 8, inlet_D=6.0, inlet_u=0.05, noise_amp=0.2, noise_seed=5, A=5e-3)
     p = make_params(prob)
     N = prob.n_nodes
@@ -210,20 +220,23 @@ def test_first_step_blue_loss_through_inlet_face(orc, lat):
     assert abs(lost - rest_only) > 1e-6
 
 
-def _inflow_closed_forms(prob, orc, t, inlet_uz=None):
+def _inflow_closed_forms(prob, orc, t, lat, inlet_uz=None):
     """Red mass and momentum streamed out of the inlet ghost plane in one step.
 
     Each ghost cell holds f^e_i = rho_r0 [varphi_i(alpha_r) + w_i P_i(u)] and
-    sends its nine c_z = +1 populations to z = 0.  With the indicator
-    [c_z = 1] = (c_z + c_z^2)/2 and the D3Q27 lattice sums (a tensor product of
-    the 1-D weights 1/6, 2/3, 1/6: sum w c_a^(2k) = 1/3), the moments of the
-    equilibrium give per cell
+    sends its c_z = +1 populations (nine on D3Q27, five on D3Q19) to z = 0.
+    With the indicator [c_z = 1] = (c_z + c_z^2)/2 and the lattice sums
+    sum w c_a^2 = sum w c_a^4 = 1/3, sum w c_a^2 c_b^2 = sum w c_a^4 c_b^2 = 1/9
+    (both lattices) and s = sum w c_x^2 c_y^2 c_z^2 (1/27 on D3Q27, 0 on D3Q19),
+    the moments of the equilibrium give per cell
         mass = z-momentum = (rho_r0/2) (kappa_r/3 + u_z + u_z^2),
-        x-momentum = (rho_r0 u_x/2) (1/3 + u_z + u_z^2)   (y alike),
-    kappa_r = 27 (1 - alpha_r)/19, independent of the radial part of u except
-    through u_x, u_y themselves."""
+        x-momentum = (rho_r0 u_x/2) (1/3 + u_z + u_z^2 + 13.5 (s - 1/27) u_y^2)
+        (y alike with u_x^2), kappa_r = (1 - alpha_r)/(1 - w_0), independent of
+    the radial part of u except through u_x, u_y themselves."""
     nx, ny = prob.nx, prob.ny
-    kap = _kappa(prob.alpha_r)
+    c, w = lat
+    kap = _kappa(prob.alpha_r, w[0])
+    s = float((w * c[:, 0] ** 2 * c[:, 1] ** 2 * c[:, 2] ** 2).sum())
     mass = 0.0
     mom = np.zeros(3)
     for y in range(ny):
@@ -238,8 +251,8 @@ def _inflow_closed_forms(prob, orc, t, inlet_uz=None):
             uz = prob.inlet_u if inlet_uz is None else inlet_uz[y * nx + x]
             m = 0.5 * prob.rho_r0 * (kap / 3 + uz + uz * uz)
             mass += m
-            mom += [0.5 * prob.rho_r0 * ux * (1 / 3 + uz + uz * uz),
-                    0.5 * prob.rho_r0 * uy * (1 / 3 + uz + uz * uz), m]
+            mom += [0.5 * prob.rho_r0 * ux * (1 / 3 + uz + uz * uz + 13.5 * (s - 1 / 27) * uy * uy),
+                    0.5 * prob.rho_r0 * uy * (1 / 3 + uz + uz * uz + 13.5 * (s - 1 / 27) * ux * ux), m]
     return mass, mom
 
 
@@ -257,7 +270,7 @@ def test_first_step_red_inflow_matches_closed_forms(orc, lat, t0, profile):
         iu = np.random.default_rng(4).uniform(0.02, 0.08, prob.nx * prob.ny)
     fr, fb, h = orc.init_fields(p, np.zeros(N), np.full(N, prob.rho_b0))
     orc.step(p, prob.A, fr, fb, h, t0, 1, inlet_uz=iu)
-    m_exp, mom_exp = _inflow_closed_forms(prob, orc, t0, iu)
+    m_exp, mom_exp = _inflow_closed_forms(prob, orc, t0, lat, iu)
     assert m_exp > 0 and np.abs(mom_exp[:2]).max() > 1e-4 * m_exp
     assert abs(fr.sum() - m_exp) < 1e-13 * m_exp
     mom = np.array([(fr * c[:, a][:, None]).sum() for a in range(3)])
@@ -266,7 +279,7 @@ def test_first_step_red_inflow_matches_closed_forms(orc, lat, t0, profile):
     x, y, z = _grid(prob)
     assert np.abs(fr[:, z > 0]).max() == 0.0
     # another time level draws other noise
-    m2, mom2 = _inflow_closed_forms(prob, orc, t0 + 1, iu)
+    m2, mom2 = _inflow_closed_forms(prob, orc, t0 + 1, lat, iu)
     assert np.abs(mom2[:2] - mom_exp[:2]).max() > 1e-3 * np.abs(mom_exp[:2]).max()
 
 
@@ -309,6 +322,7 @@ def test_outlet_convective_rule_at_new_time_level(orc, lat):
     assert np.abs(fr[:, top] - exp_r).max() < 1e-15
     assert np.abs(fb[:, top] - exp_b).max() < 1e-15
     # the history holds the new outlet plane (red then blue)
+    Q = len(c)
     assert np.array_equal(h[:Q], fr[:, top]) and np.array_equal(h[Q:], fb[:, top])
     # lambda at time t would have given a different plane: the test discriminates
     lam_t = np.maximum(uz_t, 0.0)
