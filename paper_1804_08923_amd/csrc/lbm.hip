@@ -115,9 +115,8 @@ int validate(const lbm_params* p)
     if (p->lattice != 0 && p->lattice != 27 && p->lattice != 19)
         return fail(LBM_ERR_INVALID_ARG, "unknown lattice %d (19 or 27)", p->lattice);
     if (is_q19(p)) {
-        if (p->bc != LBM_BC_PERIODIC || p->storage != LBM_STORAGE_FP32)
-            return fail(LBM_ERR_UNSUPPORTED, "the D3Q19 lattice is implemented for periodic lattices in FP32 only");
-        if (p->init == LBM_INIT_JET) return fail(LBM_ERR_UNSUPPORTED, "the jet preset needs the D3Q27 lattice");
+        if (p->storage != LBM_STORAGE_FP32)
+            return fail(LBM_ERR_UNSUPPORTED, "the D3Q19 lattice is implemented with FP32 storage only");
         if ((uint64_t)p->nx * p->ny * p->nz > (1ull << 31))
             return fail(LBM_ERR_UNSUPPORTED, "the D3Q19 lattice holds at most 2^31 nodes");
     }
@@ -336,7 +335,7 @@ int lbm_query_sizes(const lbm_params* p, lbm_sizes* out)
     if (is_q19(p)) {
         out->pop_bytes = q19::pop_bytes(N);
         out->field_bytes = 16ull * N;
-        out->hist_bytes = 0;
+        out->hist_bytes = p->bc == LBM_BC_JET ? 2ull * 2ull * q19::Q19 * plane * sizeof(float) : 0;
         out->audit_bytes = (nblk + 1) * 5 * sizeof(double);
         out->inlet_bytes = plane * sizeof(float);
         out->adjoint_bytes = 0;
@@ -417,6 +416,8 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
         H->XR = nullptr;
         H->own[0].R = H->own[1].R = nullptr;
         H->own[0].Q = H->own[1].Q = nullptr;
+        H->own[0].hist = p->bc == LBM_BC_JET ? buf->hist : nullptr;
+        H->own[1].hist = p->bc == LBM_BC_JET ? buf->hist + 2 * (size_t)q19::Q19 * H->k.plane : nullptr;
         const double ar = 1.0 - (1.0 - p->alpha_b) * p->rho_b0 / p->rho_r0;
         hipLaunchKernelGGL(q19::k19_init, H->grid_all, dim3(BLOCK), 0, H->stream, (float*)H->own[0].pop, H->k,
                            p->init, rho_r, rho_b, u, p->drop_cx, p->drop_cy, p->drop_cz, p->drop_R, p->drop_W,
@@ -453,11 +454,46 @@ namespace {
 
 // One full time step from the current state into the state set dst, which
 // becomes the current state.
-int q19_step(lbm_handle* h, const StateSet& dst_set, int dst_cs)
+template <int BC>
+int q19_launch(lbm_handle* h, const StateSet& dst_set, hipEvent_t* e)
 {
     const KP k = read_kp(h);
     const float* src = (const float*)cur_set(h).pop;
     float* dst = (float*)dst_set.pop;
+    const float* hprev = cur_set(h).hist;
+    float* hcur = dst_set.hist;
+    // jet: the planes below the outlet, then the outlet plane by its own kernel
+    const dim3 gd = BC == LBM_BC_JET ? dim3(h->grid_all.x, (unsigned)(h->p.nz - 1)) : h->grid_all;
+    if (h->unshifted)
+        hipLaunchKernelGGL((q19::k19_density<true, BC>), gd, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
+    else
+        hipLaunchKernelGGL((q19::k19_density<false, BC>), gd, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
+    LAUNCH_CHECK();
+    if (BC == LBM_BC_JET) {
+        if (h->unshifted)
+            hipLaunchKernelGGL(q19::k19_outlet<true>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->PD4, hprev,
+                               hcur, k);
+        else
+            hipLaunchKernelGGL(q19::k19_outlet<false>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->PD4, hprev,
+                               hcur, k);
+        LAUNCH_CHECK();
+    }
+    if (e) {
+        HIP_CHECK(hipEventRecord(e[1], h->stream));
+        HIP_CHECK(hipEventRecord(e[2], h->stream));
+    }
+    if (h->unshifted)
+        hipLaunchKernelGGL((q19::k19_collide<true, BC>), h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4,
+                           hcur, k);
+    else
+        hipLaunchKernelGGL((q19::k19_collide<false, BC>), h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4,
+                           hcur, k);
+    LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+int q19_step(lbm_handle* h, const StateSet& dst_set, int dst_cs)
+{
     hipEvent_t* e = nullptr;
     if (h->profiling) {
         while (h->ev.size() < h->ev_used + 5) {
@@ -469,20 +505,9 @@ int q19_step(lbm_handle* h, const StateSet& dst_set, int dst_cs)
         h->ev_used += 5;
         HIP_CHECK(hipEventRecord(e[0], h->stream));
     }
-    if (h->unshifted)
-        hipLaunchKernelGGL(q19::k19_density<true>, h->grid_all, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
-    else
-        hipLaunchKernelGGL(q19::k19_density<false>, h->grid_all, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
-    LAUNCH_CHECK();
-    if (e) {
-        HIP_CHECK(hipEventRecord(e[1], h->stream));
-        HIP_CHECK(hipEventRecord(e[2], h->stream));
-    }
-    if (h->unshifted)
-        hipLaunchKernelGGL(q19::k19_collide<true>, h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4, k);
-    else
-        hipLaunchKernelGGL(q19::k19_collide<false>, h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4, k);
-    LAUNCH_CHECK();
+    const int rc = h->p.bc == LBM_BC_JET ? q19_launch<LBM_BC_JET>(h, dst_set, e)
+                                         : q19_launch<LBM_BC_PERIODIC>(h, dst_set, e);
+    if (rc != LBM_OK) return rc;
     if (e) {
         HIP_CHECK(hipEventRecord(e[3], h->stream));
         HIP_CHECK(hipEventRecord(e[4], h->stream));
@@ -641,13 +666,18 @@ int lbm_macroscopic(lbm_handle* h, float* rho_r, float* rho_b, float* u, float* 
     const KP k = read_kp(h);
     int rc = h->q19 ? [&]() -> int {
         const float* pop = (const float*)cur_set(h).pop;
+        const float* hist = cur_set(h).hist;
         double* part = audit ? h->audit : nullptr;
+        const bool jet = h->p.bc == LBM_BC_JET;
         if (h->unshifted)
-            hipLaunchKernelGGL(q19::k19_macro<true>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, rho_r, rho_b,
-                               u, phi, part);
+            hipLaunchKernelGGL((q19::k19_macro<true, LBM_BC_PERIODIC>), h->grid_all, dim3(BLOCK), 0, h->stream, pop,
+                               hist, k, rho_r, rho_b, u, phi, part);
+        else if (jet)
+            hipLaunchKernelGGL((q19::k19_macro<false, LBM_BC_JET>), h->grid_all, dim3(BLOCK), 0, h->stream, pop, hist,
+                               k, rho_r, rho_b, u, phi, part);
         else
-            hipLaunchKernelGGL(q19::k19_macro<false>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, rho_r, rho_b,
-                               u, phi, part);
+            hipLaunchKernelGGL((q19::k19_macro<false, LBM_BC_PERIODIC>), h->grid_all, dim3(BLOCK), 0, h->stream, pop,
+                               hist, k, rho_r, rho_b, u, phi, part);
         LAUNCH_CHECK();
         return LBM_OK;
     }() : dispatch(h->p.bc, h->p.storage, [&](auto bc, auto st) -> int {
@@ -677,10 +707,16 @@ int lbm_get_state(lbm_handle* h, float* state)
     const KP k = read_kp(h);
     if (h->q19) {
         const float* pop = (const float*)cur_set(h).pop;
+        const float* hist = cur_set(h).hist;
         if (h->unshifted)
-            hipLaunchKernelGGL(q19::k19_get_state<true>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, state);
+            hipLaunchKernelGGL((q19::k19_get_state<true, LBM_BC_PERIODIC>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                               pop, hist, k, state);
+        else if (h->p.bc == LBM_BC_JET)
+            hipLaunchKernelGGL((q19::k19_get_state<false, LBM_BC_JET>), h->grid_all, dim3(BLOCK), 0, h->stream, pop,
+                               hist, k, state);
         else
-            hipLaunchKernelGGL(q19::k19_get_state<false>, h->grid_all, dim3(BLOCK), 0, h->stream, pop, k, state);
+            hipLaunchKernelGGL((q19::k19_get_state<false, LBM_BC_PERIODIC>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                               pop, hist, k, state);
         LAUNCH_CHECK();
         return LBM_OK;
     }

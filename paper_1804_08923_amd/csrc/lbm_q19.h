@@ -11,7 +11,7 @@
 //   B_i          -1/3 at rest, w_i otherwise (Eq. B_i): sum B_i = 1/3;
 //   moments      the 19 rows of Eq. momentSet that are independent on D3Q19,
 //                relaxed with s0, s1, s2nu, s2b, s3, s4 (Eq. scoll).
-// Periodic lattices and FP32 storage; the arithmetic is FP64 (the kernels are
+// Periodic and jet lattices, FP32 storage; the arithmetic is FP64 (the kernels are
 // bound by memory traffic, and FP32 arithmetic would add about 1e-5 of the
 // spurious velocity of a resting droplet to the FP32 storage floor).  Node
 // index n = (z ny + y) nx + x with no padding; the periodic wrap is taken on
@@ -85,18 +85,20 @@ constexpr uint32_t kXcds = 8;
 
 struct Site {
     uint32_t n;                    // node index
-    uint32_t xs[3], ys[3], zs[3];  // x - 1, x, x + 1; (y - 1, y, y + 1) nx; (z - 1, z, z + 1) nx ny
+    uint32_t q;                    // y nx + x
+    int x, y, z;
+    uint32_t xs[3], ys[3], zs[3];  // periodic: x - 1, x, x + 1; (y - 1, y, y + 1) nx; (z - 1, z, z + 1) nx ny
     bool valid;
 };
 
-__device__ __forceinline__ Site site(const KP& k)
+__device__ __forceinline__ Site site(const KP& k, int zoff = 0)
 {
     Site s;
     const uint32_t B = gridDim.x, b = blockIdx.x;
     const uint32_t pb = (B % kXcds == 0) ? (b % kXcds) * (B / kXcds) + b / kXcds : b;
     const uint32_t p = pb * (uint32_t)BLOCK + threadIdx.x;
     s.valid = p < k.plane;
-    const int z = (int)blockIdx.y;
+    const int z = (int)blockIdx.y + zoff;
     const int y = (int)(((uint64_t)p * k.nx_mul) >> k.nx_sh);
     const int x = (int)p - y * k.nx;
     s.xs[0] = x == 0 ? k.nx - 1 : x - 1;
@@ -109,6 +111,10 @@ __device__ __forceinline__ Site site(const KP& k)
     s.zs[1] = (uint32_t)z * k.plane;
     s.zs[2] = (uint32_t)(z == k.nz - 1 ? 0 : z + 1) * k.plane;
     s.n = s.zs[1] + p;
+    s.q = p;
+    s.x = x;
+    s.y = y;
+    s.z = z;
     return s;
 }
 
@@ -123,81 +129,219 @@ __device__ __forceinline__ const float4* records(const float* pop, uint64_t N)
     return (const float4*)((const char*)pop + rec_offset(N));
 }
 
-// Population i streamed into this node: its deviation d and its red part fr
-// (general form: read at the node; shifted form: rebuilt from the producing
-// node's deviation and record).  The blue part is d + w_i rho_b0 - fr.
-template <bool GEN>
-__device__ __forceinline__ void pulled(const float* __restrict__ pop, const KP& k, const Site& s, int i, double& d,
-                                       double& fr)
+// Jet boundaries (Sec. IV A), with the rules the D3Q27 path uses: a circular
+// inlet at z = -1/2 whose ghost cells hold the red equilibrium of the inflow
+// (with the seeded radial noise of the time level the populations left it),
+// half-way free-slip walls at x, y = -1/2, n - 1/2 and z = -1/2 (specular
+// reflection: the population of the clamped node with the outside components
+// reversed), and the convective outflow of the top plane.
+
+// inlet ghost population of direction i leaving ghost column (xg, yg) at
+// post-collision time tg: red equilibrium at rho_r0, alpha_r, Phi = 0
+__device__ __forceinline__ double inlet_feq19(const KP& k, int i, int xg, int yg, long long tg)
+{
+    const uint64_t cnt = ((uint64_t)tg * (uint64_t)k.ny + (uint64_t)yg) * (uint64_t)k.nx + (uint64_t)xg;
+    const uint64_t r = splitmix64_nth(k.seed, cnt);
+    const double xi = (double)(r >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    const double ur = (double)k.noise_amp * (double)k.inlet_u * xi;
+    const double dx = (double)xg - (double)k.inlet_cx, dy = (double)yg - (double)k.inlet_cy;
+    const double rr = sqrt(dx * dx + dy * dy);
+    const double ux = rr > 0.0 ? ur * dx / rr : 0.0, uy = rr > 0.0 ? ur * dy / rr : 0.0;
+    const double uz = k.inlet_uz ? (double)k.inlet_uz[yg * k.nx + xg] : (double)k.inlet_u;
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    const double cu = kCX[i] * ux + kCY[i] * uy + kCZ[i] * uz;
+    const double poly = cu * (3.0 + 4.5 * cu + 4.5 * cu * cu - 4.5 * u2) - 1.5 * u2;
+    const double ph = i == 0 ? (double)k.alpha_r : 1.5 * w19(i) * (1.0 - (double)k.alpha_r);
+    return (double)k.rho_r0 * (ph + w19(i) * poly);
+}
+
+// colour of population j of the shifted form at node src (Eqs. op3r/op3b)
+__device__ __forceinline__ void shifted_pop(const float* __restrict__ pop, const KP& k, int j, uint32_t src,
+                                            double& d, double& fr)
 {
     const size_t N = k.N;
-    if constexpr (GEN) {
-        d = (double)pop[(size_t)i * N + s.n];
-        const double mn = (double)pop[(size_t)(Q19 + i) * N + s.n];
-        const bool blue_min = pop[(size_t)(2 * Q19) * N + s.n] != 0.f;
-        fr = blue_min ? d + w19(i) * k.rho_b0 - mn : mn;
+    d = (double)pop[(size_t)j * N + src];
+    const float4 r = records(pop, N)[src];
+    const double f = d + w19(j) * k.rho_b0;
+    const double rec = j ? krec(j) * ((double)kCX[j] * r.y + (double)kCY[j] * r.z + (double)kCZ[j] * r.w) : 0.0;
+    fr = signbit(r.x) ? f - (-(double)r.x * f - rec) : (double)r.x * f + rec;
+}
+
+// Population i streamed into node (x, y, z) of the shifted form: its deviation
+// d and its red part fr (the blue part is d + w_i rho_b0 - fr).  Not for the
+// jet's outlet plane, which the convective rule fills.
+template <int BC>
+__device__ __forceinline__ void pull_at(const float* __restrict__ pop, const KP& k, const Site& s, int x, int y,
+                                        int z, int i, double& d, double& fr)
+{
+    if constexpr (BC == LBM_BC_PERIODIC) {
+        (void)x;
+        (void)y;
+        (void)z;
+        shifted_pop(pop, k, i, at(s, -kCX[i], -kCY[i], -kCZ[i]), d, fr);
     } else {
-        const uint32_t src = at(s, -kCX[i], -kCY[i], -kCZ[i]);
-        d = (double)pop[(size_t)i * N + src];
-        const float4 r = records(pop, N)[src];
-        const double f = d + w19(i) * k.rho_b0;
-        const double rec = i ? krec(i) * ((double)kCX[i] * r.y + (double)kCY[i] * r.z + (double)kCZ[i] * r.w) : 0.0;
-        fr = signbit(r.x) ? f - (-(double)r.x * f - rec) : (double)r.x * f + rec;
+        int sx = x - kCX[i], sy = y - kCY[i], sz = z - kCZ[i];
+        if (sz < 0 && inlet_inside(k, sx, sy)) {
+            fr = inlet_feq19(k, i, sx, sy, k.t - 1);  // left the inlet at the previous time level
+            d = fr - w19(i) * k.rho_b0;
+            return;
+        }
+        int m = 0;
+        if (sx < 0 || sx >= k.nx) { m |= 1; sx = x; }
+        if (sy < 0 || sy >= k.ny) { m |= 2; sy = y; }
+        if (sz < 0) { m |= 4; sz = z; }
+        const int j = m ? (int)kMirror.v[i * 8 + m] : i;
+        shifted_pop(pop, k, j, ((uint32_t)sz * (uint32_t)k.ny + (uint32_t)sy) * (uint32_t)k.nx + (uint32_t)sx, d, fr);
     }
 }
 
-// d_i only (the collision does not need the colours)
-template <bool GEN>
-__device__ __forceinline__ float deviation(const float* __restrict__ pop, const KP& k, const Site& s, int i)
+// general form at the node
+__device__ __forceinline__ void general_pop(const float* __restrict__ pop, const KP& k, uint32_t n, int i, double& d,
+                                            double& fr)
 {
     const size_t N = k.N;
-    if constexpr (GEN) return pop[(size_t)i * N + s.n];
-    return pop[(size_t)i * N + at(s, -kCX[i], -kCY[i], -kCZ[i])];
+    d = (double)pop[(size_t)i * N + n];
+    const double mn = (double)pop[(size_t)(Q19 + i) * N + n];
+    const bool blue_min = pop[(size_t)(2 * Q19) * N + n] != 0.f;
+    fr = blue_min ? d + w19(i) * k.rho_b0 - mn : mn;
 }
 
-// sums of both colours over the streamed populations; the minority colour is
-// summed from its own parts
-template <bool GEN>
-__device__ __forceinline__ void colour_sums(const float* __restrict__ pop, const KP& k, const Site& s, double& rr,
-                                            double& rb, double& m)
+// The jet's outlet plane after streaming by the convective rule (Lou et al.):
+// f(N, t) = [f(N, t - 1) + lam f(N - 1, t)] / (1 + lam), lam = max(0, u_z(N - 1, t))
+// with u_z of the freshly streamed plane below (half-force term included);
+// hist holds f(N, t - 1) as (d, fr) planes.  Both colours.
+__device__ __forceinline__ void outlet_rule(const float* __restrict__ pop, const float* __restrict__ hist,
+                                            const KP& k, const Site& s, double (&d)[Q19], double (&fr)[Q19])
 {
-    rr = 0.0;
-    rb = 0.0;
-    m = 0.0;
+    double m = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < Q19; ++i) {
-        double d, fr;
-        pulled<GEN>(pop, k, s, i, d, fr);
-        m += d;
-        rr += fr;
-        rb += d + w19(i) * k.rho_b0 - fr;
+        pull_at<LBM_BC_JET>(pop, k, s, s.x, s.y, k.nz - 2, i, d[i], fr[i]);
+        m += d[i];
+        if (kCZ[i]) jz += kCZ[i] * d[i];
+    }
+    const double uz = (jz + 0.5 * m * k.gz) / (k.rho_b0 + m);
+    const double lam = uz > 0.0 ? uz : 0.0, il = 1.0 / (1.0 + lam);
+    const size_t P = k.plane;
+#pragma unroll
+    for (int i = 0; i < Q19; ++i) {
+        d[i] = ((double)hist[(size_t)i * P + s.q] + lam * d[i]) * il;
+        fr[i] = ((double)hist[(size_t)(Q19 + i) * P + s.q] + lam * fr[i]) * il;
     }
 }
 
-// Density pass (Eq. order): PD[n] = (phi, rho - rho_b0, rho_r, rho_b).
-template <bool GEN>
+// The state at this node: the populations after streaming, (d_i, fr_i), of
+// either form; the jet's outlet plane from the general form, or by the rule.
+template <bool GEN, int BC>
+__device__ __forceinline__ void node_state(const float* __restrict__ pop, const float* __restrict__ hist, const KP& k,
+                                           const Site& s, double (&d)[Q19], double (&fr)[Q19])
+{
+    if (GEN) {
+#pragma unroll
+        for (int i = 0; i < Q19; ++i) general_pop(pop, k, s.n, i, d[i], fr[i]);
+    } else if (BC == LBM_BC_JET && s.z == k.nz - 1) {
+        outlet_rule(pop, hist, k, s, d, fr);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q19; ++i) pull_at<BC>(pop, k, s, s.x, s.y, s.z, i, d[i], fr[i]);
+    }
+}
+
+// Density pass (Eq. order): PD[n] = (phi, rho - rho_b0, rho_r, rho_b), on the
+// planes below the jet's outlet (all planes when periodic).
+template <bool GEN, int BC>
 __global__ __launch_bounds__(BLOCK) void k19_density(const float* __restrict__ pop, float4* __restrict__ PD, KP k)
 {
     const Site s = site(k);
     if (!s.valid) return;
-    double rr, rb, m;
-    colour_sums<GEN>(pop, k, s, rr, rb, m);
+    double rr = 0.0, rb = 0.0, m = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q19; ++i) {
+        double d, fr;
+        if (GEN)
+            general_pop(pop, k, s.n, i, d, fr);
+        else
+            pull_at<BC>(pop, k, s, s.x, s.y, s.z, i, d, fr);
+        m += d;
+        rr += fr;
+        rb += d + w19(i) * k.rho_b0 - fr;
+    }
     const double a = rr / k.rho_r0, b = rb / k.rho_b0;
     PD[s.n] = make_float4((float)((a - b) / (a + b)), (float)m, (float)rr, (float)rb);
 }
 
+// The jet's outlet plane (one plane, blockIdx.y = 0): its populations after
+// streaming (general form, or the convective rule from hprev) go to hcur as
+// (d, fr), where the collision and the next step's rule read them, and its
+// densities to PD.
+template <bool GEN>
+__global__ __launch_bounds__(BLOCK) void k19_outlet(const float* __restrict__ pop, float4* __restrict__ PD,
+                                                    const float* __restrict__ hprev, float* __restrict__ hcur, KP k)
+{
+    const Site s = site(k, k.nz - 1);
+    if (!s.valid) return;
+    double d[Q19], fr[Q19];
+    node_state<GEN, LBM_BC_JET>(pop, hprev, k, s, d, fr);
+    double rr = 0.0, rb = 0.0, m = 0.0;
+    const size_t P = k.plane;
+#pragma unroll
+    for (int i = 0; i < Q19; ++i) {
+        m += d[i];
+        rr += fr[i];
+        rb += d[i] + w19(i) * k.rho_b0 - fr[i];
+        hcur[(size_t)i * P + s.q] = (float)d[i];
+        hcur[(size_t)(Q19 + i) * P + s.q] = (float)fr[i];
+    }
+    const double a = rr / k.rho_r0, b = rb / k.rho_b0;
+    PD[s.n] = make_float4((float)((a - b) / (a + b)), (float)m, (float)rr, (float)rb);
+}
+
+// (phi, rho - rho_b0) of the neighbour at offset (dx, dy, dz): periodic wrap,
+// or (jet) (1, rho_r0 - rho_b0) in the inlet circle at z = -1 and the clamped
+// node elsewhere outside (the mirrored field of the half-way walls and outlet)
+template <int BC>
+__device__ __forceinline__ float2 field_at(const float4* __restrict__ PD, const KP& k, const Site& s, int dx, int dy,
+                                           int dz)
+{
+    if constexpr (BC == LBM_BC_PERIODIC) {
+        const float4 q = PD[at(s, dx, dy, dz)];
+        return make_float2(q.x, q.y);
+    } else {
+        int x = s.x + dx, y = s.y + dy, z = s.z + dz;
+        if (z < 0 && inlet_inside(k, x, y)) return make_float2(1.f, k.rho_r0 - k.rho_b0);
+        x = x < 0 ? 0 : (x >= k.nx ? k.nx - 1 : x);
+        y = y < 0 ? 0 : (y >= k.ny ? k.ny - 1 : y);
+        z = z < 0 ? 0 : (z >= k.nz ? k.nz - 1 : z);
+        const float4 q = PD[((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x];
+        return make_float2(q.x, q.y);
+    }
+}
+
 // Collision, perturbation, recolouring and the store of the shifted form at the
 // node itself (the next step pulls from it), Sec. II: Eqs. Momentum to op3b.
-template <bool GEN>
+template <bool GEN, int BC>
 __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ src, float* __restrict__ dst,
-                                                     const float4* __restrict__ PD, KP k)
+                                                     const float4* __restrict__ PD, const float* __restrict__ hcur,
+                                                     KP k)
 {
     const Site s = site(k);
     if (!s.valid) return;
     const size_t N = k.N;
     float d[Q19];
+    if (BC == LBM_BC_JET && s.z == k.nz - 1) {  // the outlet plane: the density pass wrote it to hcur
 #pragma unroll
-    for (int i = 0; i < Q19; ++i) d[i] = deviation<GEN>(src, k, s, i);
+        for (int i = 0; i < Q19; ++i) d[i] = hcur[(size_t)i * k.plane + s.q];
+    } else if (GEN) {
+#pragma unroll
+        for (int i = 0; i < Q19; ++i) d[i] = src[(size_t)i * N + s.n];
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q19; ++i) {
+            double dd, fr;
+            pull_at<BC>(src, k, s, s.x, s.y, s.z, i, dd, fr);
+            d[i] = (float)dd;
+        }
+    }
     const float4 P = PD[s.n];
     const double phi = P.x, m = P.y, rr = P.z, rb = P.w;
     // isotropic gradients of phi and rho, 3 sum_i w_i chi(x + c_i) c_i, summed
@@ -206,8 +350,8 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
     double gpx = 0, gpy = 0, gpz = 0, grx = 0, gry = 0, grz = 0;
 #pragma unroll
     for (int i = 1; i < Q19; i += 2) {
-        const float4 qp = PD[at(s, kCX[i], kCY[i], kCZ[i])];
-        const float4 qm = PD[at(s, -kCX[i], -kCY[i], -kCZ[i])];
+        const float2 qp = field_at<BC>(PD, k, s, kCX[i], kCY[i], kCZ[i]);
+        const float2 qm = field_at<BC>(PD, k, s, -kCX[i], -kCY[i], -kCZ[i]);
         const double tp = 3.0 * w19(i) * ((double)qp.x - (double)qm.x);
         const double tr = 3.0 * w19(i) * ((double)qp.y - (double)qm.y);
         if (kCX[i]) { gpx += kCX[i] * tp; grx += kCX[i] * tr; }
@@ -325,25 +469,26 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
 }
 
 // Macroscopic fields (node order) and FP64 audit partial sums, one slot per block.
-template <bool GEN>
-__global__ __launch_bounds__(BLOCK) void k19_macro(const float* __restrict__ pop, KP k, float* __restrict__ o_rr,
-                                                   float* __restrict__ o_rb, float* __restrict__ o_u,
-                                                   float* __restrict__ o_phi, double* __restrict__ partials)
+template <bool GEN, int BC>
+__global__ __launch_bounds__(BLOCK) void k19_macro(const float* __restrict__ pop, const float* __restrict__ hist, KP k,
+                                                   float* __restrict__ o_rr, float* __restrict__ o_rb,
+                                                   float* __restrict__ o_u, float* __restrict__ o_phi,
+                                                   double* __restrict__ partials)
 {
     const Site s = site(k);
     double acc[5] = {0, 0, 0, 0, 0};
     if (s.valid) {
+        double d[Q19], fv[Q19];
+        node_state<GEN, BC>(pop, hist, k, s, d, fv);
         double m0 = 0.0, rr = 0.0, rb = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
         for (int i = 0; i < Q19; ++i) {
-            double d, fr;
-            pulled<GEN>(pop, k, s, i, d, fr);
-            m0 += d;
-            rr += fr;
-            rb += d + w19(i) * k.rho_b0 - fr;
-            if (kCX[i]) jx += kCX[i] * d;
-            if (kCY[i]) jy += kCY[i] * d;
-            if (kCZ[i]) jz += kCZ[i] * d;
+            m0 += d[i];
+            rr += fv[i];
+            rb += d[i] + w19(i) * k.rho_b0 - fv[i];
+            if (kCX[i]) jx += kCX[i] * d[i];
+            if (kCY[i]) jy += kCY[i] * d[i];
+            if (kCZ[i]) jz += kCZ[i] * d[i];
         }
         const double rho = (double)k.rho_b0 + m0;
         const double px = jx + 0.5 * m0 * k.gx, py = jy + 0.5 * m0 * k.gy, pz = jz + 0.5 * m0 * k.gz;
@@ -369,18 +514,19 @@ __global__ __launch_bounds__(BLOCK) void k19_macro(const float* __restrict__ pop
 }
 
 // the state fr[i N + n], fb[(19 + i) N + n] of either form
-template <bool GEN>
-__global__ __launch_bounds__(BLOCK) void k19_get_state(const float* __restrict__ pop, KP k, float* __restrict__ st)
+template <bool GEN, int BC>
+__global__ __launch_bounds__(BLOCK) void k19_get_state(const float* __restrict__ pop, const float* __restrict__ hist,
+                                                       KP k, float* __restrict__ st)
 {
     const Site s = site(k);
     if (!s.valid) return;
     const size_t N = k.N;
+    double d[Q19], fr[Q19];
+    node_state<GEN, BC>(pop, hist, k, s, d, fr);
 #pragma unroll
     for (int i = 0; i < Q19; ++i) {
-        double d, fr;
-        pulled<GEN>(pop, k, s, i, d, fr);
-        st[(size_t)i * N + s.n] = (float)fr;
-        st[(size_t)(Q19 + i) * N + s.n] = (float)(d + w19(i) * k.rho_b0 - fr);
+        st[(size_t)i * N + s.n] = (float)fr[i];
+        st[(size_t)(Q19 + i) * N + s.n] = (float)(d[i] + w19(i) * k.rho_b0 - fr[i]);
     }
 }
 
@@ -439,6 +585,9 @@ __global__ __launch_bounds__(BLOCK) void k19_init(float* __restrict__ dst, KP k,
         const double th = tanh(2.0 * (sqrt(dx * dx + dy * dy + dz * dz) - R) / W);
         rr = 0.5 * rho_r0 * (1.0 - th);
         rb = 0.5 * rho_b0 * (1.0 + th);
+    } else if (kind == LBM_INIT_JET) {
+        rr = 0.0;
+        rb = rho_b0;
     } else {
         rr = frr[s.n];
         rb = frb[s.n];

@@ -109,9 +109,9 @@ def test_null_handle_is_rejected(lib):
 
 
 def test_q19_sizes_and_validation(lib):
-    """lattice = 19 (D3Q19): buffer sizes of its two state forms, and the
-    configurations it does not implement (16-bit storage, the jet) are
-    LBM_ERR_UNSUPPORTED; a lattice other than 19 or 27 is invalid."""
+    """lattice = 19 (D3Q19): buffer sizes of its two state forms and of the
+    jet's outlet history; 16-bit storage is LBM_ERR_UNSUPPORTED; a lattice
+    other than 19 or 27, or a bad inlet, is invalid."""
     prob = droplet_small().replace(lattice=19, alpha_b=1 / 3, nx=13, ny=7, nz=5)
     s = lbm.lbm_query_sizes(lbm.make_params(prob))
     N = 13 * 7 * 5
@@ -122,9 +122,12 @@ def test_q19_sizes_and_validation(lib):
     assert s.snap_bytes == 0 and s.adjoint_bytes == 0 and s.hist_bytes == 0
     big = prob.replace(nx=256, ny=256, nz=1024)
     assert lbm.lbm_query_sizes(lbm.make_params(big)).pop_bytes == 39 * 256 * 256 * 1024 * 4
+    jet = jet_128().replace(lattice=19, alpha_b=1 / 3)
+    sj = lbm.lbm_query_sizes(lbm.make_params(jet))
+    assert sj.hist_bytes == 2 * 2 * 19 * 128 * 128 * 4 and sj.snap_bytes == 0
     r = lbm.lbm_sizes()
-    for bad, code in ((prob.replace(storage="bf16"), -2), (jet_128().replace(lattice=19, alpha_b=1 / 3), -2),
-                      (prob.replace(init="jet"), -2), (prob.replace(lattice=23), -1)):
+    for bad, code in ((prob.replace(storage="bf16"), -2), (jet.replace(storage="fp16"), -2),
+                      (prob.replace(lattice=23), -1), (jet.replace(inlet_D=130.0), -1)):
         assert lib.lbm_query_sizes(C.byref(lbm.make_params(bad)), C.byref(r)) == code
         assert lib.lbm_last_error().decode() != ""
     # 0 (a zeroed parameter block) still means D3Q27

@@ -184,6 +184,78 @@ def test_q19_laplace_table1_gamma1(torch):
     assert umax < 1e-4
 
 
+def _q19_jet(name, nx, ny, nz, D, Re, We, steps, seed):
+    from paper_1804_08923_amd.workloads import jet_problem
+    return jet_problem(name, nx, ny, nz, D=D, u=0.04, gamma=2.0, eta=1.0, Re=Re, We=We, Fr=2.0, steps=steps,
+                       noise_amp=0.01, noise_seed=seed).replace(lattice=19, alpha_b=1.0 / 3.0)
+
+
+@pytest.mark.parametrize("steps", [1, 150])
+def test_q19_small_jet(torch, o19, steps):
+    """The jet boundaries on D3Q19 (inflow ghost with seeded noise, free-slip
+    walls, convective outflow) and buoyancy on a 20x18x40 lattice from the
+    all-blue start: fields to 1e-5 (rel L-inf), every population of both
+    colours to 1e-5 of the population scale, and the FP64 audit against the
+    oracle's colour masses.  Then the oracle's state at step s is handed over
+    with lbm_set_state at time level s and both sides take 10 more steps (the
+    inlet noise depends on the time level)."""
+    prob = _q19_jet("q19-jet-small", 20, 18, 40, 8, 40.0, 20.0, 150, 7)
+    say(f"D3Q19 small jet {steps} steps")
+    sim = _sim(prob)
+    sim.step(steps)
+    fg = gpu_fields(sim)
+    a0 = sim.macroscopic(audit=True)["audit"]
+    p = or_params(prob)
+    N = prob.n_nodes
+    fr, fb, h = o19.init_fields(p, np.zeros(N), np.full(N, prob.rho_b0))
+    o19.step(p, prob.A, fr, fb, h, 0, steps)
+    rr, rb, u, ph = o19.macroscopic(p, fr, fb)
+    fo = dict(rho=rr + rb, u=u, phi=ph, rho_r=rr)
+    errs = {k: rel_linf(fg[k], fo[k]) for k in fo}
+    say(f"  rel Linf {errs}")
+    for k, e in errs.items():
+        assert e <= 1e-5, k
+    assert abs(a0[0] / rr.sum() - 1) < 1e-5 and abs(a0[1] / rb.sum() - 1) < 1e-6
+    gr, gb = _gpu_state(sim)
+    scale = np.abs(fr + fb).max()
+    err = max(np.abs(gr - fr).max(), np.abs(gb - fb).max()) / scale
+    say(f"  max pop err {err:.2e}")
+    assert err < 1e-5
+    # hand-over at time level `steps`
+    st = np.concatenate([fr, fb], axis=0).astype(np.float32)
+    fr, fb = st[:Q19].astype(np.float64), st[Q19:].astype(np.float64)
+    sim.set_state(torch.from_numpy(st).cuda(), t=steps)
+    sim.step(10)
+    h = np.concatenate([fr, fb], axis=0)[:, (prob.nz - 1) * prob.nx * prob.ny:].copy()
+    o19.step(p, prob.A, fr, fb, h, steps, 10)
+    gr, gb = _gpu_state(sim)
+    sim.close()
+    err = max(np.abs(gr - fr).max(), np.abs(gb - fb).max()) / scale
+    say(f"  after set_state at t = {steps} and 10 steps: max pop err {err:.2e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("shape,D", [((3, 3, 3), 2.0), ((20, 5, 4), 3.0), ((64, 32, 6), 5.0)])
+def test_q19_tiny_jets(torch, o19, shape, D):
+    """The D3Q19 jet where almost every node is next to a wall, the inlet or
+    the outlet (the 3x3x3 minimum), and on a 64x32 plane (8 blocks, in XCD
+    bands): 30 steps against the oracle, every population."""
+    prob = _q19_jet("q19-jet-tiny", *shape, D, 20.0, 10.0, 30, 5)
+    say(f"D3Q19 tiny jet {shape} D={D}")
+    sim = _sim(prob)
+    sim.step(prob.steps)
+    gr, gb = _gpu_state(sim)
+    sim.close()
+    p = or_params(prob)
+    N = prob.n_nodes
+    fr, fb, h = o19.init_fields(p, np.zeros(N), np.full(N, prob.rho_b0))
+    o19.step(p, prob.A, fr, fb, h, 0, prob.steps)
+    scale = np.abs(fr + fb).max()
+    err = max(np.abs(gr - fr).max(), np.abs(gb - fb).max()) / scale
+    say(f"  max pop err {err:.2e}")
+    assert err < 1e-5
+
+
 def test_q19_unsupported_entry_points(torch):
     """Snapshots, the adjoint step and the jet diagnostics need the D3Q27
     lattice: each returns LBM_ERR_UNSUPPORTED on a D3Q19 handle and leaves it
