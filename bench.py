@@ -18,8 +18,9 @@ duration in the profiled pass, against the 8 TB/s HBM peak.
 cpu_baseline = the FP64 oracle on the host cores, on a bounded slab sample of
 the same jet, on all threads and on one.
 lattices = the reduced D3Q19 lattice (Sec. II's suggested cost cut) against
-D3Q27 on a periodic droplet box of the same size (the jet boundaries exist
-for D3Q27 only), each with its own kernel timings and roofline.
+D3Q27: on the same jet (developed and timed like the headline leg) and on a
+periodic droplet box of the same size, each with its own kernel timings and
+roofline.
 """
 from __future__ import annotations
 
@@ -236,6 +237,63 @@ def lattice_legs(jet, steps, warmup):
     return out
 
 
+def q19_jet_leg(jet, steps, warmup, main_leg, chunk=250):
+    """D3Q19 on the headline jet itself (alpha_b = 1/3 gives the coolant
+    c_s^2 = 1/3), run for the headline leg's warmup + steps in chunks of
+    `chunk` steps, each timed with events, with the FP64 audit between them
+    (outside the timed region): the rate is taken over every chunk run while
+    the state was finite, and the first step at which it was not is reported."""
+    import torch
+
+    from paper_1804_08923_amd.lbm import LBM, LbmError
+    prob = jet.replace(lattice=19, alpha_b=1.0 / 3.0)
+    sim = LBM(prob, device="cuda:0")
+    N = prob.n_nodes
+    stream = sim.stream
+    nonfinite_at = None
+    timed_ms, timed_steps = 0.0, 0
+    done = 0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    while done < warmup + steps:
+        k = min(chunk, warmup + steps - done)
+        e0.record(stream)
+        sim.step(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        try:
+            sim.macroscopic(audit=True)
+        except LbmError as err:
+            if err.code != -4:
+                raise
+            nonfinite_at = done + k
+            break
+        timed_ms += e0.elapsed_time(e1)
+        timed_steps += k
+        done += k
+    kms = [0.0, 0.0]
+    if nonfinite_at is None:
+        sim.profile(True)
+        sim.step(PROFILE_STEPS)
+        ms, launches = sim.profile_read()
+        sim.profile(False)
+        kms = [ms[0] / launches[0], ms[1] / launches[1]]
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    fb, db = Q19_FUSED_BYTES, Q19_DENSITY_BYTES
+    mlups = N * timed_steps / (timed_ms * 1e-3) / 1e6 if timed_steps else None
+    out = {"workload": prob.name, "timed_steps": timed_steps, "mlups": round(mlups, 1) if mlups else None,
+           "x_d3q27": round(mlups / main_leg["mlups"], 3) if mlups else None,
+           "nonfinite_at_step": nonfinite_at, "finite": nonfinite_at is None}
+    if nonfinite_at is None:
+        out.update({"fused_kernel_ms": round(kms[1], 4), "density_kernel_ms": round(kms[0], 4),
+                    "fused_kernel_gbs": round(fb * N / (kms[1] * 1e-3) / 1e9, 1),
+                    "step_roofline_frac": round(mlups / (HBM_PEAK_GBS * 1e9 / Q19_STEP_BYTES / 1e6), 4)})
+    log(f"bench: {prob.name} D3Q19: {out['mlups']} MLUPS over {timed_steps} timed steps "
+        f"({out['x_d3q27']}x D3Q27); non-finite at step {nonfinite_at}")
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -352,6 +410,7 @@ def main():
     if not args.no_lattices:
         lat = lattice_legs(prob, args.lattice_steps, 200)
         log(f"bench: D3Q19 / D3Q27 on {lat['workload']}: {lat['d3q19_x_d3q27']:.2f}x")
+        lat["jet"] = q19_jet_leg(prob, args.steps, args.warmup, main_leg)
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")

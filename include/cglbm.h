@@ -99,9 +99,10 @@ typedef struct lbm_params {
        alpha_b = 1/3 gives c_s^2 = 1/3); Phi_i = -3 nu_bar u.grad rho at rest and
        m_i nu_bar (c.u)(c.grad rho)/4 with m = 2 (faces), 1 (edges); B_i = -1/3
        at rest and w_i otherwise; the 19 rows of Eq. momentSet that are
-       independent on D3Q19.  D3Q19 supports bc == LBM_BC_PERIODIC, storage
-       FP32 and the fields and droplet presets (else LBM_ERR_UNSUPPORTED), at
-       most 2^31 nodes, and the entry points lbm_query_sizes, lbm_init,
+       independent on D3Q19.  D3Q19 supports both boundary kinds (the jet with
+       the same inlet, free-slip and outflow rules), FP32 storage only (else
+       LBM_ERR_UNSUPPORTED), the three presets, at most 2^31 nodes, and the
+       entry points lbm_query_sizes, lbm_init,
        lbm_step, lbm_macroscopic, lbm_get_state, lbm_set_state, lbm_time,
        lbm_profile, lbm_profile_read and lbm_destroy; the snapshot, adjoint
        and jet-diagnostics calls return LBM_ERR_UNSUPPORTED.  Q below is 27,
@@ -122,7 +123,7 @@ typedef struct lbm_sizes {
                                (19 with the reference records of BF16_EQ / FP16_EQ; D3Q19:
                                4 floats per node) */
     uint64_t hist_bytes;    /* outlet planes of the previous and current step, 2 x 54 floats
-                               per (x, y); jet only */
+                               per (x, y) (D3Q19: 2 x 38); jet only */
     uint64_t audit_bytes;   /* FP64 partial sums of the audit reduction */
     uint64_t inlet_bytes;   /* optional inlet axial-velocity profile, nx*ny floats */
     uint64_t adjoint_bytes; /* adjoint work buffer (see lbm_adjoint_step) */

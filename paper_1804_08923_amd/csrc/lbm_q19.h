@@ -171,27 +171,37 @@ __device__ __forceinline__ void shifted_pop(const float* __restrict__ pop, const
 // d and its red part fr (the blue part is d + w_i rho_b0 - fr).  Not for the
 // jet's outlet plane, which the convective rule fills.
 template <int BC>
-__device__ __forceinline__ void pull_at(const float* __restrict__ pop, const KP& k, const Site& s, int x, int y,
-                                        int z, int i, double& d, double& fr)
+__device__ __forceinline__ void pull_at(const float* __restrict__ pop, const KP& k, const Site& s, int i, double& d,
+                                        double& fr)
 {
     if constexpr (BC == LBM_BC_PERIODIC) {
-        (void)x;
-        (void)y;
-        (void)z;
         shifted_pop(pop, k, i, at(s, -kCX[i], -kCY[i], -kCZ[i]), d, fr);
     } else {
-        int sx = x - kCX[i], sy = y - kCY[i], sz = z - kCZ[i];
-        if (sz < 0 && inlet_inside(k, sx, sy)) {
-            fr = inlet_feq19(k, i, sx, sy, k.t - 1);  // left the inlet at the previous time level
+        const int cx = kCX[i], cy = kCY[i], cz = kCZ[i];
+        // the source x - c_i lies outside along an axis: reflect there (the
+        // walls act per axis; selects, no branch, so the loads of the 19
+        // directions issue together)
+        const bool ox = cx > 0 ? s.x == 0 : (cx < 0 ? s.x == k.nx - 1 : false);
+        const bool oy = cy > 0 ? s.y == 0 : (cy < 0 ? s.y == k.ny - 1 : false);
+        const bool oz = cz > 0 && s.z == 0;
+        if (oz && inlet_inside(k, s.x - cx, s.y - cy)) {  // only on the bottom plane
+            fr = inlet_feq19(k, i, s.x - cx, s.y - cy, k.t - 1);  // left the inlet at the previous time level
             d = fr - w19(i) * k.rho_b0;
             return;
         }
-        int m = 0;
-        if (sx < 0 || sx >= k.nx) { m |= 1; sx = x; }
-        if (sy < 0 || sy >= k.ny) { m |= 2; sy = y; }
-        if (sz < 0) { m |= 4; sz = z; }
-        const int j = m ? (int)kMirror.v[i * 8 + m] : i;
-        shifted_pop(pop, k, j, ((uint32_t)sz * (uint32_t)k.ny + (uint32_t)sy) * (uint32_t)k.nx + (uint32_t)sx, d, fr);
+        const int m = (ox ? 1 : 0) | (oy ? 2 : 0) | (oz ? 4 : 0);
+        const int j = m == 0 ? i : m == 1 ? mirror_dir(i, 1) : m == 2 ? mirror_dir(i, 2) : m == 3 ? mirror_dir(i, 3)
+                    : m == 4 ? mirror_dir(i, 4) : m == 5 ? mirror_dir(i, 5) : m == 6 ? mirror_dir(i, 6)
+                    : mirror_dir(i, 7);
+        const int off = (ox ? 0 : cx) + (oy ? 0 : cy) * k.nx + (oz ? 0 : cz) * (int)k.plane;
+        const uint32_t src = (uint32_t)((int)s.n - off);
+        const size_t N = k.N;
+        d = (double)pop[(size_t)j * N + src];
+        const float4 r = records(pop, N)[src];
+        const double f = d + w19(i) * k.rho_b0;
+        const double jx = ox ? -cx : cx, jy = oy ? -cy : cy, jz = oz ? -cz : cz;  // c_j
+        const double rec = i ? krec(i) * (jx * r.y + jy * r.z + jz * r.w) : 0.0;
+        fr = signbit(r.x) ? f - (-(double)r.x * f - rec) : (double)r.x * f + rec;
     }
 }
 
@@ -213,10 +223,13 @@ __device__ __forceinline__ void general_pop(const float* __restrict__ pop, const
 __device__ __forceinline__ void outlet_rule(const float* __restrict__ pop, const float* __restrict__ hist,
                                             const KP& k, const Site& s, double (&d)[Q19], double (&fr)[Q19])
 {
+    Site below = s;  // the plane under the outlet
+    below.z = k.nz - 2;
+    below.n = s.n - k.plane;
     double m = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < Q19; ++i) {
-        pull_at<LBM_BC_JET>(pop, k, s, s.x, s.y, k.nz - 2, i, d[i], fr[i]);
+        pull_at<LBM_BC_JET>(pop, k, below, i, d[i], fr[i]);
         m += d[i];
         if (kCZ[i]) jz += kCZ[i] * d[i];
     }
@@ -243,7 +256,7 @@ __device__ __forceinline__ void node_state(const float* __restrict__ pop, const 
         outlet_rule(pop, hist, k, s, d, fr);
     } else {
 #pragma unroll
-        for (int i = 0; i < Q19; ++i) pull_at<BC>(pop, k, s, s.x, s.y, s.z, i, d[i], fr[i]);
+        for (int i = 0; i < Q19; ++i) pull_at<BC>(pop, k, s, i, d[i], fr[i]);
     }
 }
 
@@ -261,7 +274,7 @@ __global__ __launch_bounds__(BLOCK) void k19_density(const float* __restrict__ p
         if (GEN)
             general_pop(pop, k, s.n, i, d, fr);
         else
-            pull_at<BC>(pop, k, s, s.x, s.y, s.z, i, d, fr);
+            pull_at<BC>(pop, k, s, i, d, fr);
         m += d;
         rr += fr;
         rb += d + w19(i) * k.rho_b0 - fr;
@@ -307,12 +320,13 @@ __device__ __forceinline__ float2 field_at(const float4* __restrict__ PD, const 
         const float4 q = PD[at(s, dx, dy, dz)];
         return make_float2(q.x, q.y);
     } else {
-        int x = s.x + dx, y = s.y + dy, z = s.z + dz;
-        if (z < 0 && inlet_inside(k, x, y)) return make_float2(1.f, k.rho_r0 - k.rho_b0);
-        x = x < 0 ? 0 : (x >= k.nx ? k.nx - 1 : x);
-        y = y < 0 ? 0 : (y >= k.ny ? k.ny - 1 : y);
-        z = z < 0 ? 0 : (z >= k.nz ? k.nz - 1 : z);
-        const float4 q = PD[((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x];
+        if (dz < 0 && s.z == 0 && inlet_inside(k, s.x + dx, s.y + dy))  // bottom plane only
+            return make_float2(1.f, k.rho_r0 - k.rho_b0);
+        // clamp per axis (selects)
+        const int ex = (s.x + dx < 0 || s.x + dx >= k.nx) ? 0 : dx;
+        const int ey = (s.y + dy < 0 || s.y + dy >= k.ny) ? 0 : dy;
+        const int ez = (s.z + dz < 0 || s.z + dz >= k.nz) ? 0 : dz;
+        const float4 q = PD[(uint32_t)((int)s.n + ex + ey * k.nx + ez * (int)k.plane)];
         return make_float2(q.x, q.y);
     }
 }
@@ -338,7 +352,7 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
 #pragma unroll
         for (int i = 0; i < Q19; ++i) {
             double dd, fr;
-            pull_at<BC>(src, k, s, s.x, s.y, s.z, i, dd, fr);
+            pull_at<BC>(src, k, s, i, dd, fr);
             d[i] = (float)dd;
         }
     }
