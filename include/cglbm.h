@@ -104,8 +104,9 @@ typedef struct lbm_params {
        LBM_ERR_UNSUPPORTED), the three presets, at most 2^31 nodes, and the
        entry points lbm_query_sizes, lbm_init,
        lbm_step, lbm_macroscopic, lbm_get_state, lbm_set_state, lbm_time,
-       lbm_profile, lbm_profile_read and lbm_destroy; the snapshot, adjoint
-       and jet-diagnostics calls return LBM_ERR_UNSUPPORTED.  Q below is 27,
+       the jet diagnostics (both forms), lbm_profile, lbm_profile_read and
+       lbm_destroy; the snapshot and adjoint calls return
+       LBM_ERR_UNSUPPORTED.  Q below is 27,
        or 19 for D3Q19. */
     int32_t lattice;
     int32_t lattice_pad;  /* unused */

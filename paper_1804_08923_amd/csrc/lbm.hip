@@ -947,8 +947,16 @@ int diag_run(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, 
         constexpr int BC = decltype(bc)::value;
         hipLaunchKernelGGL(k_diag_clear, dim3(1), dim3(64), 0, h->stream, w);
         LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_diag_init<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
-                           (const typename S::T*)cur_set(h).pop, cur_set(h).hist, k, w);
+        const float* hist = cur_set(h).hist;
+        if (!h->q19)
+            hipLaunchKernelGGL((k_diag_init<BC, S>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                               (const typename S::T*)cur_set(h).pop, hist, k, w);
+        else if (h->unshifted)
+            hipLaunchKernelGGL((q19::k19_diag_init<true, BC>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                               (const float*)cur_set(h).pop, hist, k, w);
+        else
+            hipLaunchKernelGGL((q19::k19_diag_init<false, BC>), h->grid_all, dim3(BLOCK), 0, h->stream,
+                               (const float*)cur_set(h).pop, hist, k, w);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_diag_merge, h->grid_all, dim3(BLOCK), 0, h->stream, k, w);
         LAUNCH_CHECK();
@@ -984,7 +992,6 @@ int diag_run(lbm_handle* h, void* work, lbm_jet_stats* stats, int64_t* volumes, 
 int diag_args(lbm_handle* h, lbm_jet_stats* stats, int64_t* volumes, int64_t cap)
 {
     if (!h) return fail(LBM_ERR_STATE, "handle is NULL");
-    if (h->q19) return fail(LBM_ERR_UNSUPPORTED, "the jet diagnostics need the D3Q27 lattice");
     if (!stats) return fail(LBM_ERR_INVALID_ARG, "stats is required");
     if (cap < 0 || (cap > 0 && !volumes)) return fail(LBM_ERR_INVALID_ARG, "volumes is NULL with cap > 0");
     return LBM_OK;

@@ -47,6 +47,7 @@
 // its FP32 error inside a phase would leave a noisy grad phi for the
 // perturbation to turn into velocity.
 #pragma once
+#include "lbm_diag.h"
 #include "lbm_kernels.h"
 
 namespace cglbm {
@@ -541,6 +542,38 @@ __global__ __launch_bounds__(BLOCK) void k19_get_state(const float* __restrict__
     for (int i = 0; i < Q19; ++i) {
         st[(size_t)i * N + s.n] = (float)fr[i];
         st[(size_t)(Q19 + i) * N + s.n] = (float)(d[i] + w19(i) * k.rho_b0 - fr[i]);
+    }
+}
+
+// Jet diagnostics (Sec. IV C), first pass on D3Q19: the order parameter of the
+// current state binarised (phi as lbm_macroscopic returns it), labels and
+// counters; the union-find passes that follow are those of the D3Q27 path.
+template <bool GEN, int BC>
+__global__ __launch_bounds__(BLOCK) void k19_diag_init(const float* __restrict__ pop, const float* __restrict__ hist,
+                                                       KP k, DiagWork w)
+{
+    const Site s = site(k);
+    bool fg = false;
+    if (s.valid) {
+        double d[Q19], fr[Q19];
+        node_state<GEN, BC>(pop, hist, k, s, d, fr);
+        double rr = 0.0, rb = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q19; ++i) {
+            rr += fr[i];
+            rb += d[i] + w19(i) * k.rho_b0 - fr[i];
+        }
+        const double a = rr / k.rho_r0, b = rb / k.rho_b0;
+        fg = (float)((a - b) / (a + b)) > 0.f;
+        w.label[s.n] = fg ? (int)s.n : -1;
+        w.count[s.n] = 0;
+        w.column[s.n] = 0;
+    }
+    const unsigned long long m = __ballot(fg);
+    const int zmax = wave_max_int(fg ? s.z : -1);
+    if ((threadIdx.x & 63) == 0 && m) {
+        atomicAdd(&w.hdr->jet_nodes, (unsigned long long)__popcll(m));
+        atomicMax(&w.hdr->front_z, zmax);
     }
 }
 

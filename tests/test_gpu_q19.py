@@ -256,16 +256,48 @@ def test_q19_tiny_jets(torch, o19, shape, D):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("case", ["blobs", "jet"])
+def test_q19_jet_diagnostics(torch, case):
+    """The jet diagnostics of Sec. IV C on D3Q19 handles against the CPU
+    reference on the same order-parameter field (the GPU's own phi from
+    lbm_macroscopic), exactly: seeded random blobs in the general form the
+    fields preset writes (periodic, 33 x 65 x 17), and a D3Q19 jet after 300
+    steps in the shifted form; the static-workspace entry point agrees."""
+    from oracle.diagnostics import jet_diagnostics
+    from synth import sphere_blobs
+
+    from paper_1804_08923_amd.lbm import LBM
+    if case == "blobs":
+        nx, ny, nz = 33, 65, 17
+        phi = sphere_blobs(nx, ny, nz, 3, 150)
+        prob = _prob(nx, ny, nz, init="fields", inlet_cx=(nx - 1) / 2, inlet_cy=(ny - 1) / 2, inlet_D=4.0)
+        rr = (prob.rho_r0 * (1 + phi) / 2).astype(np.float32)
+        rb = (prob.rho_b0 * (1 - phi) / 2).astype(np.float32)
+        sim = LBM(prob, rho_r=torch.from_numpy(rr), rho_b=torch.from_numpy(rb))
+    else:
+        prob = _q19_jet("q19-jet-diag", 32, 30, 64, 10, 200.0, 20.0, 300, 9)
+        sim = LBM(prob)
+        sim.step(300)
+    stats, vol = sim.jet_diagnostics()
+    phi = sim.macroscopic()["phi"].cpu().numpy()
+    ref, rvol = jet_diagnostics(phi, prob.nx, prob.ny, prob.nz)
+    say(f"  D3Q19 {case}: {stats}, {len(vol)} fragments")
+    assert stats == ref and np.array_equal(vol, rvol)
+    assert stats["jet_nodes"] > 100
+    s2, v2 = sim.jet_diagnostics_static(len(vol) + 1)
+    assert s2 == stats and np.array_equal(v2, vol)
+    sim.close()
+
+
 def test_q19_unsupported_entry_points(torch):
-    """Snapshots, the adjoint step and the jet diagnostics need the D3Q27
-    lattice: each returns LBM_ERR_UNSUPPORTED on a D3Q19 handle and leaves it
-    usable."""
+    """Snapshots and the adjoint step need the D3Q27 lattice: each returns
+    LBM_ERR_UNSUPPORTED on a D3Q19 handle and leaves it usable."""
     from paper_1804_08923_amd.lbm import LbmError
     prob = _prob(8, 8, 8)
     sim = _sim(prob)
     snap = torch.empty(256, dtype=torch.uint8, device="cuda")
     for call in (lambda: sim.step_to_snapshot(snap), lambda: sim.save_snapshot(snap),
-                 lambda: sim.load_snapshot(snap, 0), lambda: sim.jet_diagnostics_static(4)):
+                 lambda: sim.load_snapshot(snap, 0)):
         with pytest.raises(LbmError) as ei:
             call()
         assert ei.value.code == -2
