@@ -45,7 +45,7 @@ struct lbm_handle {
     int cs;             // current set: 0 or 1 (own), 2 (ext)
     float2* PD;         // (phi, rho - rho_b0) per padded node
     float* XR;          // tagged minority-colour fraction per padded node
-    float4* PD4;        // D3Q19: (phi, rho - rho_b0, rho_r, rho_b) per node
+    float2* F2;         // D3Q19: (phi, rho - rho_b0) per node, then (rho_r, rho_b) per node
     double* audit;
     void* adjoint;
     hipStream_t stream;
@@ -411,7 +411,7 @@ int lbm_init(lbm_handle** h, const lbm_params* p, const lbm_buffers* buf, const 
     H->grid_shell = dim3((unsigned)((cells + BLOCK - 1) / BLOCK));
     H->nblk = (int)(H->grid_all.x * H->grid_all.y);
     if (H->q19) {
-        H->PD4 = (float4*)buf->fields;
+        H->F2 = (float2*)buf->fields;
         H->PD = nullptr;
         H->XR = nullptr;
         H->own[0].R = H->own[1].R = nullptr;
@@ -465,16 +465,16 @@ int q19_launch(lbm_handle* h, const StateSet& dst_set, hipEvent_t* e)
     // jet: the planes below the outlet, then the outlet plane by its own kernel
     const dim3 gd = BC == LBM_BC_JET ? dim3(h->grid_all.x, (unsigned)(h->p.nz - 1)) : h->grid_all;
     if (h->unshifted)
-        hipLaunchKernelGGL((q19::k19_density<true, BC>), gd, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
+        hipLaunchKernelGGL((q19::k19_density<true, BC>), gd, dim3(BLOCK), 0, h->stream, src, h->F2, k);
     else
-        hipLaunchKernelGGL((q19::k19_density<false, BC>), gd, dim3(BLOCK), 0, h->stream, src, h->PD4, k);
+        hipLaunchKernelGGL((q19::k19_density<false, BC>), gd, dim3(BLOCK), 0, h->stream, src, h->F2, k);
     LAUNCH_CHECK();
     if (BC == LBM_BC_JET) {
         if (h->unshifted)
-            hipLaunchKernelGGL(q19::k19_outlet<true>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->PD4, hprev,
+            hipLaunchKernelGGL(q19::k19_outlet<true>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->F2, hprev,
                                hcur, k);
         else
-            hipLaunchKernelGGL(q19::k19_outlet<false>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->PD4, hprev,
+            hipLaunchKernelGGL(q19::k19_outlet<false>, h->grid_plane, dim3(BLOCK), 0, h->stream, src, h->F2, hprev,
                                hcur, k);
         LAUNCH_CHECK();
     }
@@ -483,10 +483,10 @@ int q19_launch(lbm_handle* h, const StateSet& dst_set, hipEvent_t* e)
         HIP_CHECK(hipEventRecord(e[2], h->stream));
     }
     if (h->unshifted)
-        hipLaunchKernelGGL((q19::k19_collide<true, BC>), h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4,
+        hipLaunchKernelGGL((q19::k19_collide<true, BC>), h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->F2,
                            hcur, k);
     else
-        hipLaunchKernelGGL((q19::k19_collide<false, BC>), h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->PD4,
+        hipLaunchKernelGGL((q19::k19_collide<false, BC>), h->grid_all, dim3(BLOCK), 0, h->stream, src, dst, h->F2,
                            hcur, k);
     LAUNCH_CHECK();
     return LBM_OK;

@@ -36,8 +36,8 @@
 //            is f_i minus the minority one (written by init and set_state, read
 //            by the first step);
 //   shifted  planes 0..18 the deviations d_i = fdag_i - w_i rho_b0 at the node
-//            that produced them, then (from byte align256(76 N)) a float4
-//            record (x, V) per node, V = beta (rho_r rho_b / rho)
+//            that produced them, then (from byte align256(76 N)) four planes
+//            of the record (x, V_x, V_y, V_z) per node, V = beta (rho_r rho_b / rho)
 //            (1 - alpha_bar) grad phi / |grad phi|: the red population pulled
 //            from x - c_i is (rho_r / rho) f_i + varphi-weighted c_i . V (Eqs.
 //            op3r/op3b), so both colours are rebuilt from 23 floats.  x holds
@@ -125,9 +125,26 @@ __device__ __forceinline__ uint32_t at(const Site& s, int dx, int dy, int dz)
     return s.zs[dz + 1] + s.ys[dy + 1] + s.xs[dx + 1];
 }
 
-__device__ __forceinline__ const float4* records(const float* pop, uint64_t N)
+// the recolouring record of the shifted form: four planes of N floats, the
+// minority fraction x, then V_x, V_y, V_z
+__device__ __forceinline__ const float* records(const float* pop, uint64_t N)
 {
-    return (const float4*)((const char*)pop + rec_offset(N));
+    return (const float*)((const char*)pop + rec_offset(N));
+}
+
+// red part of a population of value f pulled from node src along lattice
+// direction i (whose velocity, reflected at walls, is (ex, ey, ez)): only the
+// V components along which c_i is nonzero are read
+__device__ __forceinline__ double red_part(const float* __restrict__ R, size_t N, uint32_t src, int i, double f,
+                                           double ex, double ey, double ez)
+{
+    const float x = R[src];
+    double cv = 0.0;
+    if (kCX[i]) cv += ex * (double)R[N + src];
+    if (kCY[i]) cv += ey * (double)R[2 * N + src];
+    if (kCZ[i]) cv += ez * (double)R[3 * N + src];
+    const double rec = i ? krec(i) * cv : 0.0;
+    return signbit(x) ? f - (-(double)x * f - rec) : (double)x * f + rec;
 }
 
 // Jet boundaries (Sec. IV A), with the rules the D3Q27 path uses: a circular
@@ -162,10 +179,7 @@ __device__ __forceinline__ void shifted_pop(const float* __restrict__ pop, const
 {
     const size_t N = k.N;
     d = (double)pop[(size_t)j * N + src];
-    const float4 r = records(pop, N)[src];
-    const double f = d + w19(j) * k.rho_b0;
-    const double rec = j ? krec(j) * ((double)kCX[j] * r.y + (double)kCY[j] * r.z + (double)kCZ[j] * r.w) : 0.0;
-    fr = signbit(r.x) ? f - (-(double)r.x * f - rec) : (double)r.x * f + rec;
+    fr = red_part(records(pop, N), N, src, j, d + w19(j) * k.rho_b0, kCX[j], kCY[j], kCZ[j]);
 }
 
 // Population i streamed into node (x, y, z) of the shifted form: its deviation
@@ -198,11 +212,9 @@ __device__ __forceinline__ void pull_at(const float* __restrict__ pop, const KP&
         const uint32_t src = (uint32_t)((int)s.n - off);
         const size_t N = k.N;
         d = (double)pop[(size_t)j * N + src];
-        const float4 r = records(pop, N)[src];
-        const double f = d + w19(i) * k.rho_b0;
-        const double jx = ox ? -cx : cx, jy = oy ? -cy : cy, jz = oz ? -cz : cz;  // c_j
-        const double rec = i ? krec(i) * (jx * r.y + jy * r.z + jz * r.w) : 0.0;
-        fr = signbit(r.x) ? f - (-(double)r.x * f - rec) : (double)r.x * f + rec;
+        // c_j: the components of c_i, reversed along the reflecting axes
+        fr = red_part(records(pop, N), N, src, i, d + w19(i) * k.rho_b0, ox ? -cx : cx, oy ? -cy : cy,
+                      oz ? -cz : cz);
     }
 }
 
@@ -261,10 +273,21 @@ __device__ __forceinline__ void node_state(const float* __restrict__ pop, const 
     }
 }
 
-// Density pass (Eq. order): PD[n] = (phi, rho - rho_b0, rho_r, rho_b), on the
+// Per-node fields F (field buffer, two float2 arrays): F[n] = (phi, rho - rho_b0),
+// which the collision gathers from the 18 neighbours, and F[N + n] =
+// (rho_r, rho_b), which it reads at the node only.
+__device__ __forceinline__ void store_fields(float2* __restrict__ F, const KP& k, uint32_t n, double rr, double rb,
+                                             double m)
+{
+    const double a = rr / k.rho_r0, b = rb / k.rho_b0;
+    F[n] = make_float2((float)((a - b) / (a + b)), (float)m);
+    F[(size_t)k.N + n] = make_float2((float)rr, (float)rb);
+}
+
+// Density pass (Eq. order): the fields F of every node, on the
 // planes below the jet's outlet (all planes when periodic).
 template <bool GEN, int BC>
-__global__ __launch_bounds__(BLOCK) void k19_density(const float* __restrict__ pop, float4* __restrict__ PD, KP k)
+__global__ __launch_bounds__(BLOCK) void k19_density(const float* __restrict__ pop, float2* __restrict__ F, KP k)
 {
     const Site s = site(k);
     if (!s.valid) return;
@@ -280,16 +303,15 @@ __global__ __launch_bounds__(BLOCK) void k19_density(const float* __restrict__ p
         rr += fr;
         rb += d + w19(i) * k.rho_b0 - fr;
     }
-    const double a = rr / k.rho_r0, b = rb / k.rho_b0;
-    PD[s.n] = make_float4((float)((a - b) / (a + b)), (float)m, (float)rr, (float)rb);
+    store_fields(F, k, s.n, rr, rb, m);
 }
 
 // The jet's outlet plane (one plane, blockIdx.y = 0): its populations after
 // streaming (general form, or the convective rule from hprev) go to hcur as
 // (d, fr), where the collision and the next step's rule read them, and its
-// densities to PD.
+// fields to F.
 template <bool GEN>
-__global__ __launch_bounds__(BLOCK) void k19_outlet(const float* __restrict__ pop, float4* __restrict__ PD,
+__global__ __launch_bounds__(BLOCK) void k19_outlet(const float* __restrict__ pop, float2* __restrict__ F,
                                                     const float* __restrict__ hprev, float* __restrict__ hcur, KP k)
 {
     const Site s = site(k, k.nz - 1);
@@ -306,20 +328,18 @@ __global__ __launch_bounds__(BLOCK) void k19_outlet(const float* __restrict__ po
         hcur[(size_t)i * P + s.q] = (float)d[i];
         hcur[(size_t)(Q19 + i) * P + s.q] = (float)fr[i];
     }
-    const double a = rr / k.rho_r0, b = rb / k.rho_b0;
-    PD[s.n] = make_float4((float)((a - b) / (a + b)), (float)m, (float)rr, (float)rb);
+    store_fields(F, k, s.n, rr, rb, m);
 }
 
 // (phi, rho - rho_b0) of the neighbour at offset (dx, dy, dz): periodic wrap,
 // or (jet) (1, rho_r0 - rho_b0) in the inlet circle at z = -1 and the clamped
 // node elsewhere outside (the mirrored field of the half-way walls and outlet)
 template <int BC>
-__device__ __forceinline__ float2 field_at(const float4* __restrict__ PD, const KP& k, const Site& s, int dx, int dy,
+__device__ __forceinline__ float2 field_at(const float2* __restrict__ F, const KP& k, const Site& s, int dx, int dy,
                                            int dz)
 {
     if constexpr (BC == LBM_BC_PERIODIC) {
-        const float4 q = PD[at(s, dx, dy, dz)];
-        return make_float2(q.x, q.y);
+        return F[at(s, dx, dy, dz)];
     } else {
         if (dz < 0 && s.z == 0 && inlet_inside(k, s.x + dx, s.y + dy))  // bottom plane only
             return make_float2(1.f, k.rho_r0 - k.rho_b0);
@@ -327,8 +347,7 @@ __device__ __forceinline__ float2 field_at(const float4* __restrict__ PD, const 
         const int ex = (s.x + dx < 0 || s.x + dx >= k.nx) ? 0 : dx;
         const int ey = (s.y + dy < 0 || s.y + dy >= k.ny) ? 0 : dy;
         const int ez = (s.z + dz < 0 || s.z + dz >= k.nz) ? 0 : dz;
-        const float4 q = PD[(uint32_t)((int)s.n + ex + ey * k.nx + ez * (int)k.plane)];
-        return make_float2(q.x, q.y);
+        return F[(uint32_t)((int)s.n + ex + ey * k.nx + ez * (int)k.plane)];
     }
 }
 
@@ -336,7 +355,7 @@ __device__ __forceinline__ float2 field_at(const float4* __restrict__ PD, const 
 // node itself (the next step pulls from it), Sec. II: Eqs. Momentum to op3b.
 template <bool GEN, int BC>
 __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ src, float* __restrict__ dst,
-                                                     const float4* __restrict__ PD, const float* __restrict__ hcur,
+                                                     const float2* __restrict__ F, const float* __restrict__ hcur,
                                                      KP k)
 {
     const Site s = site(k);
@@ -357,16 +376,16 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
             d[i] = (float)dd;
         }
     }
-    const float4 P = PD[s.n];
-    const double phi = P.x, m = P.y, rr = P.z, rb = P.w;
+    const float2 P = F[s.n], Q = F[(size_t)k.N + s.n];
+    const double phi = P.x, m = P.y, rr = Q.x, rb = Q.y;
     // isotropic gradients of phi and rho, 3 sum_i w_i chi(x + c_i) c_i, summed
     // over the opposite pairs (i, i + 1) as differences: exactly zero on a
     // uniform field, which keeps the recolouring off there
     double gpx = 0, gpy = 0, gpz = 0, grx = 0, gry = 0, grz = 0;
 #pragma unroll
     for (int i = 1; i < Q19; i += 2) {
-        const float2 qp = field_at<BC>(PD, k, s, kCX[i], kCY[i], kCZ[i]);
-        const float2 qm = field_at<BC>(PD, k, s, -kCX[i], -kCY[i], -kCZ[i]);
+        const float2 qp = field_at<BC>(F, k, s, kCX[i], kCY[i], kCZ[i]);
+        const float2 qm = field_at<BC>(F, k, s, -kCX[i], -kCY[i], -kCZ[i]);
         const double tp = 3.0 * w19(i) * ((double)qp.x - (double)qm.x);
         const double tr = 3.0 * w19(i) * ((double)qp.y - (double)qm.y);
         if (kCX[i]) { gpx += kCX[i] * tp; grx += kCX[i] * tr; }
@@ -479,8 +498,11 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
     }
     // minority fraction: rho_r / rho, or -rho_b / rho (sign bit set, also for 0)
     const float xm = rr <= rb ? (float)(rr / rc) : -(float)(rb / rc);
-    float4* R = (float4*)((char*)dst + rec_offset(N));
-    R[s.n] = make_float4(xm, (float)(vs * gpx), (float)(vs * gpy), (float)(vs * gpz));
+    float* R = (float*)((char*)dst + rec_offset(N));
+    R[s.n] = xm;
+    R[N + s.n] = (float)(vs * gpx);
+    R[2 * N + s.n] = (float)(vs * gpy);
+    R[3 * N + s.n] = (float)(vs * gpz);
 }
 
 // Macroscopic fields (node order) and FP64 audit partial sums, one slot per block.
