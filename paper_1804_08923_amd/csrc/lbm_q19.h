@@ -185,7 +185,9 @@ __device__ __forceinline__ void shifted_pop(const float* __restrict__ pop, const
 // Population i streamed into node (x, y, z) of the shifted form: its deviation
 // d and its red part fr (the blue part is d + w_i rho_b0 - fr).  Not for the
 // jet's outlet plane, which the convective rule fills.
-template <int BC>
+// BOT: the node may lie on the bottom plane z = 0 (the only plane that sees
+// the inlet and the bottom wall); false lets the compiler drop that code
+template <int BC, bool BOT = true>
 __device__ __forceinline__ void pull_at(const float* __restrict__ pop, const KP& k, const Site& s, int i, double& d,
                                         double& fr)
 {
@@ -198,8 +200,8 @@ __device__ __forceinline__ void pull_at(const float* __restrict__ pop, const KP&
         // directions issue together)
         const bool ox = cx > 0 ? s.x == 0 : (cx < 0 ? s.x == k.nx - 1 : false);
         const bool oy = cy > 0 ? s.y == 0 : (cy < 0 ? s.y == k.ny - 1 : false);
-        const bool oz = cz > 0 && s.z == 0;
-        if (oz && inlet_inside(k, s.x - cx, s.y - cy)) {  // only on the bottom plane
+        const bool oz = BOT && cz > 0 && s.z == 0;
+        if (BOT && oz && inlet_inside(k, s.x - cx, s.y - cy)) {  // only on the bottom plane
             fr = inlet_feq19(k, i, s.x - cx, s.y - cy, k.t - 1);  // left the inlet at the previous time level
             d = fr - w19(i) * k.rho_b0;
             return;
@@ -242,7 +244,7 @@ __device__ __forceinline__ void outlet_rule(const float* __restrict__ pop, const
     double m = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < Q19; ++i) {
-        pull_at<LBM_BC_JET>(pop, k, below, i, d[i], fr[i]);
+        pull_at<LBM_BC_JET, false>(pop, k, below, i, d[i], fr[i]);
         m += d[i];
         if (kCZ[i]) jz += kCZ[i] * d[i];
     }
@@ -284,6 +286,23 @@ __device__ __forceinline__ void store_fields(float2* __restrict__ F, const KP& k
     F[(size_t)k.N + n] = make_float2((float)rr, (float)rb);
 }
 
+template <bool GEN, int BC, bool BOT>
+__device__ __forceinline__ void density_sums(const float* __restrict__ pop, const KP& k, const Site& s, double& rr,
+                                             double& rb, double& m)
+{
+#pragma unroll
+    for (int i = 0; i < Q19; ++i) {
+        double d, fr;
+        if (GEN)
+            general_pop(pop, k, s.n, i, d, fr);
+        else
+            pull_at<BC, BOT>(pop, k, s, i, d, fr);
+        m += d;
+        rr += fr;
+        rb += d + w19(i) * k.rho_b0 - fr;
+    }
+}
+
 // Density pass (Eq. order): the fields F of every node, on the
 // planes below the jet's outlet (all planes when periodic).
 template <bool GEN, int BC>
@@ -292,17 +311,10 @@ __global__ __launch_bounds__(BLOCK) void k19_density(const float* __restrict__ p
     const Site s = site(k);
     if (!s.valid) return;
     double rr = 0.0, rb = 0.0, m = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q19; ++i) {
-        double d, fr;
-        if (GEN)
-            general_pop(pop, k, s.n, i, d, fr);
-        else
-            pull_at<BC>(pop, k, s, i, d, fr);
-        m += d;
-        rr += fr;
-        rb += d + w19(i) * k.rho_b0 - fr;
-    }
+    if (BC == LBM_BC_JET && s.z == 0)  // block-uniform
+        density_sums<GEN, BC, true>(pop, k, s, rr, rb, m);
+    else
+        density_sums<GEN, BC, false>(pop, k, s, rr, rb, m);
     store_fields(F, k, s.n, rr, rb, m);
 }
 
@@ -334,20 +346,39 @@ __global__ __launch_bounds__(BLOCK) void k19_outlet(const float* __restrict__ po
 // (phi, rho - rho_b0) of the neighbour at offset (dx, dy, dz): periodic wrap,
 // or (jet) (1, rho_r0 - rho_b0) in the inlet circle at z = -1 and the clamped
 // node elsewhere outside (the mirrored field of the half-way walls and outlet)
-template <int BC>
+template <int BC, bool BOT = true>
 __device__ __forceinline__ float2 field_at(const float2* __restrict__ F, const KP& k, const Site& s, int dx, int dy,
                                            int dz)
 {
     if constexpr (BC == LBM_BC_PERIODIC) {
         return F[at(s, dx, dy, dz)];
     } else {
-        if (dz < 0 && s.z == 0 && inlet_inside(k, s.x + dx, s.y + dy))  // bottom plane only
+        if (BOT && dz < 0 && s.z == 0 && inlet_inside(k, s.x + dx, s.y + dy))  // bottom plane only
             return make_float2(1.f, k.rho_r0 - k.rho_b0);
         // clamp per axis (selects)
         const int ex = (s.x + dx < 0 || s.x + dx >= k.nx) ? 0 : dx;
         const int ey = (s.y + dy < 0 || s.y + dy >= k.ny) ? 0 : dy;
         const int ez = (s.z + dz < 0 || s.z + dz >= k.nz) ? 0 : dz;
         return F[(uint32_t)((int)s.n + ex + ey * k.nx + ez * (int)k.plane)];
+    }
+}
+
+// isotropic gradients of phi and rho, 3 sum_i w_i chi(x + c_i) c_i, summed
+// over the opposite pairs (i, i + 1) as differences: exactly zero on a
+// uniform field, which keeps the recolouring off there
+template <int BC, bool BOT>
+__device__ __forceinline__ void gradients(const float2* __restrict__ F, const KP& k, const Site& s, double& gpx,
+                                          double& gpy, double& gpz, double& grx, double& gry, double& grz)
+{
+#pragma unroll
+    for (int i = 1; i < Q19; i += 2) {
+        const float2 qp = field_at<BC, BOT>(F, k, s, kCX[i], kCY[i], kCZ[i]);
+        const float2 qm = field_at<BC, BOT>(F, k, s, -kCX[i], -kCY[i], -kCZ[i]);
+        const double tp = 3.0 * w19(i) * ((double)qp.x - (double)qm.x);
+        const double tr = 3.0 * w19(i) * ((double)qp.y - (double)qm.y);
+        if (kCX[i]) { gpx += kCX[i] * tp; grx += kCX[i] * tr; }
+        if (kCY[i]) { gpy += kCY[i] * tp; gry += kCY[i] * tr; }
+        if (kCZ[i]) { gpz += kCZ[i] * tp; grz += kCZ[i] * tr; }
     }
 }
 
@@ -368,30 +399,28 @@ __global__ __launch_bounds__(BLOCK) void k19_collide(const float* __restrict__ s
     } else if (GEN) {
 #pragma unroll
         for (int i = 0; i < Q19; ++i) d[i] = src[(size_t)i * N + s.n];
+    } else if (BC == LBM_BC_JET && s.z == 0) {  // block-uniform
+#pragma unroll
+        for (int i = 0; i < Q19; ++i) {
+            double dd, fr;
+            pull_at<BC, true>(src, k, s, i, dd, fr);
+            d[i] = (float)dd;
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < Q19; ++i) {
             double dd, fr;
-            pull_at<BC>(src, k, s, i, dd, fr);
+            pull_at<BC, false>(src, k, s, i, dd, fr);
             d[i] = (float)dd;
         }
     }
     const float2 P = F[s.n], Q = F[(size_t)k.N + s.n];
     const double phi = P.x, m = P.y, rr = Q.x, rb = Q.y;
-    // isotropic gradients of phi and rho, 3 sum_i w_i chi(x + c_i) c_i, summed
-    // over the opposite pairs (i, i + 1) as differences: exactly zero on a
-    // uniform field, which keeps the recolouring off there
     double gpx = 0, gpy = 0, gpz = 0, grx = 0, gry = 0, grz = 0;
-#pragma unroll
-    for (int i = 1; i < Q19; i += 2) {
-        const float2 qp = field_at<BC>(F, k, s, kCX[i], kCY[i], kCZ[i]);
-        const float2 qm = field_at<BC>(F, k, s, -kCX[i], -kCY[i], -kCZ[i]);
-        const double tp = 3.0 * w19(i) * ((double)qp.x - (double)qm.x);
-        const double tr = 3.0 * w19(i) * ((double)qp.y - (double)qm.y);
-        if (kCX[i]) { gpx += kCX[i] * tp; grx += kCX[i] * tr; }
-        if (kCY[i]) { gpy += kCY[i] * tp; gry += kCY[i] * tr; }
-        if (kCZ[i]) { gpz += kCZ[i] * tp; grz += kCZ[i] * tr; }
-    }
+    if (BC == LBM_BC_JET && s.z == 0)  // block-uniform
+        gradients<BC, true>(F, k, s, gpx, gpy, gpz, grx, gry, grz);
+    else
+        gradients<BC, false>(F, k, s, gpx, gpy, gpz, grx, gry, grz);
     // interpolated properties, body force, velocity (Eqs. bodyForceJet, Momentum)
     const double rho = k.rho_b0 + m;
     const double hp = 0.5 * (1.0 + phi);
